@@ -1,0 +1,158 @@
+/*
+ * msfv.h -- C ABI of the MI355X (gfx950) adaptive multiscale finite volume
+ * (MSFV) library.
+ *
+ * Method: Wu Fung & Ruthotto, "A Multiscale Method for Model Order Reduction
+ * in PDE Parameter Estimation" (arXiv:1707.07598).
+ *
+ *   forward  F_k(m) = Rx^T S_k(m) A_k(m)^{-1} S_k(m)^T Q        (eq. fwdProbRed)
+ *            A_k(m) = S_k(m)^T A(m) S_k(m)                       (eq. reducedPDE)
+ *            S_k(m) = the parameter-dependent multiscale basis   (Sec. 3.2,
+ *                     eq. multiscaleBasis_step3, rebuilt at every call)
+ *   gradient J_k(m)^T v, the transposed adaptive sensitivity     (Sec. 4.1,
+ *            eq. Jk; Sec. 4.3, eq. sensred; Sec. 4.5)
+ *
+ * Discretisation: -div(exp(m) grad u) = q on a uniform cell-centred grid with
+ * unit spacing, harmonic-mean two-point fluxes, no-flux outer boundary, and
+ * the potential fixed at coarse vertex 0 (Sec. 2.1-2.2).
+ *
+ * Conventions
+ *   - All values are FP64, all indices int32.
+ *   - cell id   = i + nx*(j + ny*k)            (x fastest; 2-D: nz = 1)
+ *   - vertex id = I + Ncx*(J + Ncy*K), Nc = ceil(n/r) per axis, vertex I of an
+ *     axis sits at cell I*r + floor(min(r, n - I*r)/2).
+ *   - Sources and receivers are sparse columns given as CSR over columns:
+ *     ptr[count+1], cell[ptr[count]], val[ptr[count]] (host arrays, copied).
+ *   - D (data), v and d_obs are Nr x Ns, column j contiguous: D[j*Nr + i].
+ *   - u (fields) is N x Ns, column j contiguous: u[j*N + cell].
+ *   - S_k is CSR by fine cell, columns ascending; A_k is CSR by vertex.
+ *
+ * Ownership and streams
+ *   - m, v, d_obs and every output pointer passed to msfv_forward,
+ *     msfv_jtv and msfv_misfit_grad are DEVICE pointers owned by the caller.
+ *     Calls are asynchronous on the problem's HIP stream; outputs are valid
+ *     after msfv_sync() (or any synchronisation of that stream).
+ *   - The library owns S_k, A_k, the coarse coefficients, all workspace and
+ *     the plan; they stay resident on the device between calls.
+ *   - Introspection calls (msfv_get_*) take HOST pointers and synchronise.
+ *
+ * Errors
+ *   - Every call returns an msfv_status; nothing throws across the ABI.
+ *     msfv_last_error() returns a thread-local message for the last failure.
+ *   - Device-side conditions (non-finite m, a local or coarse iteration that
+ *     reached its cap) are recorded on the device and reported by the next
+ *     msfv_sync(): MSFV_ENONFINITE takes precedence over MSFV_ENOCONV.
+ *     Outputs are still written in both cases.
+ *   - msfv_jtv before any msfv_forward returns MSFV_ESTATE.
+ */
+#ifndef MSFV_H
+#define MSFV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msfv_problem msfv_problem;
+
+typedef enum {
+  MSFV_OK = 0,
+  MSFV_EINVAL = -1,     /* bad argument or unsupported geometry            */
+  MSFV_ENOMEM = -2,     /* device or host allocation failed                */
+  MSFV_ENOCONV = -3,    /* a local or coarse iteration reached its cap     */
+  MSFV_ENONFINITE = -4, /* m contained NaN or Inf                          */
+  MSFV_EDEVICE = -5,    /* a HIP runtime call failed                       */
+  MSFV_ESTATE = -6      /* call out of order (e.g. jtv before forward)     */
+} msfv_status;
+
+/* Boundary data of the local problems (Sec. 3.2).
+ *   MSFV_BC_REDUCED : edges, then faces, then dual-block interiors are all
+ *                     solved with their reduced (tangential) operators, so
+ *                     the block-boundary values depend on m.
+ *   MSFV_BC_LAGRANGE: block-boundary values are products of 1-D linear
+ *                     Lagrange factors ("Piecewise Lagrange Polynomials");
+ *                     only dual-block interiors are solved.              */
+enum { MSFV_BC_REDUCED = 0, MSFV_BC_LAGRANGE = 1 };
+
+typedef struct {
+  int dim;            /* 2 or 3; for dim 2, n[2] and r[2] are ignored        */
+  int n[3];           /* fine cells per axis                                 */
+  int r[3];           /* coarsening per axis, 3 <= r <= 16                   */
+  int bc_mode;        /* MSFV_BC_REDUCED or MSFV_BC_LAGRANGE                 */
+  double local_rtol;  /* local CG stop: ||r|| <= local_rtol*||b|| (0: 1e-13) */
+  int local_maxit;    /* cap on local CG iterations (0: 1000)                */
+  double coarse_rtol; /* coarse CG stop (0: 1e-13)                           */
+  int coarse_maxit;   /* cap on coarse CG iterations (0: 20000)              */
+} msfv_config;
+
+typedef struct {
+  long long ncell;     /* N                                                  */
+  long long ncoarse;   /* Nc (columns of S_k)                                */
+  long long nnz_p;     /* nonzeros of S_k                                    */
+  long long nnz_k;     /* nonzeros of A_k                                    */
+  int nsrc;            /* Ns                                                 */
+  int nrec;            /* Nr                                                 */
+  int nblock;          /* dual-block interiors solved per basis build        */
+  int nface;           /* face entities (3-D)                                */
+  int nedge;           /* edge entities                                      */
+  long long workspace_bytes; /* device bytes held by the problem             */
+} msfv_sizes;
+
+typedef struct {
+  int local_max_it;       /* largest local CG iteration count, last call     */
+  int local_noconv;       /* local solves that hit the cap, last call        */
+  int coarse_max_it;      /* largest coarse CG iteration count, last call    */
+  int coarse_noconv;      /* coarse solves that hit the cap, last call       */
+  int nonfinite;          /* 1 if m contained NaN/Inf                        */
+} msfv_stats;
+
+/* Create a problem for one grid; builds the plan (entity tables, CSR
+ * structure of S_k and A_k) and allocates its device state.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Unsupported geometry (r outside
+ * [3, 16], n < 2r on some axis) returns MSFV_EINVAL. */
+msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem** out);
+
+/* Release all device and host state.  NULL is ignored. */
+void msfv_destroy(msfv_problem* p);
+
+/* Set the sources Q (Sec. 2.1, q_j) as sparse columns (host arrays). */
+msfv_status msfv_set_sources(msfv_problem* p, int ns, const int* ptr, const int* cell,
+                             const double* val);
+
+/* Set the receivers Rx (Sec. 2.1, p_i) as sparse columns (host arrays). */
+msfv_status msfv_set_receivers(msfv_problem* p, int nr, const int* ptr, const int* cell,
+                               const double* val);
+
+/* Forward problem (eq. fwdProbRed): rebuild S_k(m) and A_k(m), solve the
+ * pinned coarse system for every source, write D = Rx^T S_k t (d_out, Nr*Ns)
+ * and, if u_out != NULL, the fields u = S_k t (N*Ns).  m: device, N values. */
+msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double* u_out);
+
+/* Gradient g = J_k(m)^T v at the m of the last msfv_forward (Sec. 4.3,
+ * transposed): v device Nr*Ns (same layout as D), g_out device N. */
+msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out);
+
+/* Misfit phi = 1/2 ||D(m) - d_obs||_F^2 (Sec. 2.2) and its gradient
+ * J_k^T (D - d_obs): forward + jtv.  phi_out: device, 1 value. */
+msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_obs,
+                             double* phi_out, double* g_out);
+
+/* Wait for the problem's stream; returns MSFV_ENONFINITE / MSFV_ENOCONV if
+ * the last forward or jtv recorded that condition, else MSFV_OK. */
+msfv_status msfv_sync(msfv_problem* p);
+
+/* Introspection (host copies; synchronises).  Arrays sized by msfv_sizes:
+ * row_ptr N+1, col nnz_p, val nnz_p (S_k); row_ptr Nc+1, col nnz_k,
+ * val nnz_k (A_k before fixing vertex 0), t_out Nc*Ns (coarse
+ * coefficients, column j contiguous).  Any pointer may be NULL. */
+msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out);
+msfv_status msfv_get_prolongation(msfv_problem* p, int* row_ptr, int* col, double* val);
+msfv_status msfv_get_coarse(msfv_problem* p, int* row_ptr, int* col, double* val, double* t_out);
+msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out);
+
+const char* msfv_status_string(msfv_status s);
+const char* msfv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSFV_H */

@@ -1,0 +1,273 @@
+"""MI355X-native adaptive multiscale finite volume (MSFV) hot path.
+
+Implements, as hand-written HIP kernels for gfx950 behind the C ABI of
+include/msfv.h, the per-iteration rebuild of the parameter-dependent
+prolongation S_k(m) (Sec. 3.2), the Galerkin reduced solve (eq. reducedPDE,
+eq. fwdProbRed) and the explicit misfit gradient through the change of basis
+(Sec. 4.3, eq. sensred; Sec. 4.5) of Wu Fung & Ruthotto (arXiv:1707.07598).
+
+This module only marshals arguments: torch provides device memory and the
+stream, every arithmetic step runs in libmsfv.so.
+
+Layouts: m and g are flat (N,) float64 CUDA tensors in cell-id order
+(x fastest); data D, residuals v and observed data are (Ns, Nr) float64
+tensors (row j = source j), i.e. the column-contiguous Nr x Ns layout of
+the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import MSFV_BC_LAGRANGE, MSFV_BC_REDUCED, MsfvError  # noqa: F401
+
+__all__ = ["Problem", "MSFVForward", "msfv_misfit", "MsfvError"]
+
+_MODES = {"reduced": MSFV_BC_REDUCED, "lagrange": MSFV_BC_LAGRANGE}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ivec(a) -> Tuple[np.ndarray, object]:
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _dvec(a) -> Tuple[np.ndarray, object]:
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Problem:
+    """One MSFV problem (grid, coarsening, boundary mode) with its device
+    state: plan, S_k, A_k, coarse coefficients and workspace stay resident
+    between calls."""
+
+    def __init__(self, n: Sequence[int], r: Sequence[int], bc_mode: str = "reduced",
+                 local_rtol: float = 1e-13, local_maxit: int = 1000,
+                 coarse_rtol: float = 1e-13, coarse_maxit: int = 20000,
+                 device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        n = tuple(int(x) for x in n)
+        r = tuple(int(x) for x in r)
+        if len(n) not in (2, 3) or len(r) != len(n):
+            raise ValueError("n and r must both have length 2 or 3")
+        self.n, self.r, self.dim = n, r, len(n)
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        cfg = _lib.MsfvConfig()
+        cfg.dim = self.dim
+        for k in range(3):
+            cfg.n[k] = n[k] if k < self.dim else 1
+            cfg.r[k] = r[k] if k < self.dim else 1
+        cfg.bc_mode = _MODES[bc_mode]
+        cfg.local_rtol = local_rtol
+        cfg.local_maxit = local_maxit
+        cfg.coarse_rtol = coarse_rtol
+        cfg.coarse_maxit = coarse_maxit
+        self.bc_mode = bc_mode
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.msfv_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
+                                            ctypes.byref(handle)), "msfv_create")
+        self._h = handle
+        self.generation = 0
+        self.last_m = None
+        self._ns = 0
+        self._nr = 0
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self.lib.msfv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- inputs ------------------------------------------------------------
+    def set_sources(self, cols) -> None:
+        ptr, pp = _ivec(cols.ptr)
+        cell, cp = _ivec(cols.cell)
+        val, vp = _dvec(cols.val)
+        _lib.check(self.lib.msfv_set_sources(self._h, int(ptr.size - 1), pp, cp, vp), "msfv_set_sources")
+        self._ns = int(ptr.size - 1)
+
+    def set_receivers(self, cols) -> None:
+        ptr, pp = _ivec(cols.ptr)
+        cell, cp = _ivec(cols.cell)
+        val, vp = _dvec(cols.val)
+        _lib.check(self.lib.msfv_set_receivers(self._h, int(ptr.size - 1), pp, cp, vp), "msfv_set_receivers")
+        self._nr = int(ptr.size - 1)
+
+    @property
+    def ns(self) -> int:
+        return self._ns
+
+    @property
+    def nr(self) -> int:
+        return self._nr
+
+    def _check_tensor(self, t, numel: int, name: str):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name} must be contiguous with {numel} elements")
+
+    # -- the path ----------------------------------------------------------
+    def forward(self, m, want_u: bool = False, out=None, sync: bool = True):
+        """D = Rx^T S_k(m) A_k(m)^{-1} S_k(m)^T Q as an (Ns, Nr) tensor; with
+        ``want_u`` also u = S_k t as an (Ns, N) tensor."""
+        torch = _torch()
+        ncell = int(np.prod(self.n))
+        self._check_tensor(m, ncell, "m")
+        D = out if out is not None else torch.empty((self._ns, self._nr), dtype=torch.float64, device=m.device)
+        u = torch.empty((self._ns, ncell), dtype=torch.float64, device=m.device) if want_u else None
+        _lib.check(self.lib.msfv_forward(self._h, _dptr(m), _dptr(D), _dptr(u) if u is not None else None),
+                   "msfv_forward")
+        self.generation += 1
+        self.last_m = m
+        if sync:
+            self.sync()
+        return (D, u) if want_u else D
+
+    def jtv(self, v, out=None, sync: bool = True):
+        """g = J_k(m)^T v at the m of the last forward; v is (Ns, Nr)."""
+        torch = _torch()
+        self._check_tensor(v, self._ns * self._nr, "v")
+        ncell = int(np.prod(self.n))
+        g = out if out is not None else torch.empty(ncell, dtype=torch.float64, device=v.device)
+        _lib.check(self.lib.msfv_jtv(self._h, _dptr(v), _dptr(g)), "msfv_jtv")
+        if sync:
+            self.sync()
+        return g
+
+    def misfit_grad(self, m, d_obs, sync: bool = True):
+        """(phi, g): phi = 1/2 ||D(m) - d_obs||_F^2 and g = J_k^T (D - d_obs)."""
+        torch = _torch()
+        ncell = int(np.prod(self.n))
+        self._check_tensor(m, ncell, "m")
+        self._check_tensor(d_obs, self._ns * self._nr, "d_obs")
+        phi = torch.empty(1, dtype=torch.float64, device=m.device)
+        g = torch.empty(ncell, dtype=torch.float64, device=m.device)
+        _lib.check(self.lib.msfv_misfit_grad(self._h, _dptr(m), _dptr(d_obs), _dptr(phi), _dptr(g)),
+                   "msfv_misfit_grad")
+        self.generation += 1
+        self.last_m = m
+        if sync:
+            self.sync()
+        return phi, g
+
+    def sync(self) -> None:
+        _lib.check(self.lib.msfv_sync(self._h), "msfv_sync")
+
+    # -- introspection -----------------------------------------------------
+    def sizes(self) -> _lib.MsfvSizes:
+        s = _lib.MsfvSizes()
+        _lib.check(self.lib.msfv_get_sizes(self._h, ctypes.byref(s)), "msfv_get_sizes")
+        return s
+
+    def stats(self) -> _lib.MsfvStats:
+        s = _lib.MsfvStats()
+        _lib.check(self.lib.msfv_get_stats(self._h, ctypes.byref(s)), "msfv_get_stats")
+        return s
+
+    def prolongation(self):
+        """S_k as (row_ptr, col, val) host arrays (CSR by fine cell)."""
+        sz = self.sizes()
+        rp = np.empty(sz.ncell + 1, np.int32)
+        col = np.empty(sz.nnz_p, np.int32)
+        val = np.empty(sz.nnz_p, np.float64)
+        _lib.check(self.lib.msfv_get_prolongation(
+            self._h, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            col.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            val.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "msfv_get_prolongation")
+        return rp, col, val
+
+    def coarse(self):
+        """A_k (before fixing vertex 0) as (row_ptr, col, val) and the coarse
+        coefficients t as an (Ns, Nc) array."""
+        sz = self.sizes()
+        rp = np.empty(sz.ncoarse + 1, np.int32)
+        col = np.empty(sz.nnz_k, np.int32)
+        val = np.empty(sz.nnz_k, np.float64)
+        t = np.empty((max(self._ns, 1), sz.ncoarse), np.float64)
+        _lib.check(self.lib.msfv_get_coarse(
+            self._h, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            col.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "msfv_get_coarse")
+        return (rp, col, val), t[: self._ns]
+
+
+def _make_function():
+    torch = _torch()
+
+    class MSFVForward(torch.autograd.Function):
+        """D = F_k(m) with backward g = J_k(m)^T grad_D (Sec. 4.1, eq. Jk).
+
+        ``MSFVForward.apply(m, problem)`` returns the (Ns, Nr) data; the
+        backward runs the library's adjoint at the same m (it re-runs the
+        forward first if the problem has been used at another m since)."""
+
+        @staticmethod
+        def forward(ctx, m, problem):
+            D = problem.forward(m.detach().contiguous())
+            ctx.problem = problem
+            ctx.generation = problem.generation
+            ctx.save_for_backward(m)
+            return D
+
+        @staticmethod
+        def backward(ctx, grad_D):
+            (m,) = ctx.saved_tensors
+            problem = ctx.problem
+            if problem.generation != ctx.generation:
+                problem.forward(m.detach().contiguous())
+                ctx.generation = problem.generation
+            g = problem.jtv(grad_D.contiguous())
+            return g, None
+
+    return MSFVForward
+
+
+class _Lazy:
+    _fn = None
+
+    def __get__(self, obj, objtype=None):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_function()
+        return _Lazy._fn
+
+
+class _Namespace:
+    MSFVForward = _Lazy()
+
+
+def __getattr__(name):
+    if name == "MSFVForward":
+        return _Namespace.MSFVForward
+    raise AttributeError(name)
+
+
+def msfv_misfit(m, problem, d_obs):
+    """phi(m) = 1/2 ||F_k(m) - d_obs||_F^2 through the autograd Function."""
+    D = _Namespace.MSFVForward.apply(m, problem)
+    return 0.5 * ((D - d_obs) ** 2).sum()

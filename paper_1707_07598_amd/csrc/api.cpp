@@ -1,0 +1,603 @@
+// C ABI of the MSFV library (declared in include/msfv.h): problem state,
+// stage sequencing on one HIP stream, and host-side bookkeeping of sources,
+// receivers and electrode loads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "msfv.h"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+msfv_status fail(msfv_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_OK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(e_ == hipErrorOutOfMemory ? MSFV_ENOMEM : MSFV_EDEVICE,                     \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t n = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(&ptr, count * sizeof(T));
+  }
+  hipError_t upload(const std::vector<T>& h, hipStream_t s) {
+    hipError_t e = alloc(h.size());
+    if (e != hipSuccess || h.empty()) return e;
+    return hipMemcpyAsync(ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+struct Columns {
+  int count = 0;
+  std::vector<int> ptr, cell;
+  std::vector<double> val;
+};
+
+}  // namespace
+
+struct msfv_problem {
+  msfv_config cfg{};
+  hipStream_t stream = nullptr;
+  msfv::Plan plan;
+  msfv::GridInfo g{};
+  Columns src, rec;
+  bool electrodes_ready = false;
+  bool have_forward = false;
+
+  // plan on the device
+  DevBuf<msfv::EntDesc> d_edges, d_faces, d_blocks;
+  DevBuf<int> d_prow, d_pcol, d_krow, d_kcol, d_kcptr, d_kcidx, d_vrows;
+  DevBuf<double> d_pval, d_kval, d_kent, d_inbuf, d_W;
+  DevBuf<double> d_m;  // copy of the m of the last forward
+  DevBuf<int> d_status;
+
+  // sources / receivers / electrodes
+  DevBuf<int> d_rptr, d_rcell;
+  DevBuf<double> d_rval;
+  DevBuf<int> d_src_dst, d_src_ptr, d_src_pidx;
+  DevBuf<double> d_src_w;
+  DevBuf<int> d_rec_dst, d_rec_ptr, d_rec_pidx, d_rec_col;
+  DevBuf<double> d_rec_w;
+  DevBuf<int> d_ecell, d_erptr, d_eridx, d_esptr, d_esidx, d_eidx, d_eloc;
+  DevBuf<double> d_erw, d_esw, d_sload;
+  int nelec = 0, nsrc_slot = 0, nrec_slot = 0;
+
+  // coarse vectors (column j contiguous) and data scratch
+  DevBuf<double> d_b, d_t, d_lam, d_D, d_v;
+
+  size_t workspace_bytes() const {
+    return d_edges.bytes() + d_faces.bytes() + d_blocks.bytes() + d_prow.bytes() + d_pcol.bytes() +
+           d_krow.bytes() + d_kcol.bytes() + d_kcptr.bytes() + d_kcidx.bytes() + d_vrows.bytes() +
+           d_pval.bytes() + d_kval.bytes() + d_kent.bytes() + d_inbuf.bytes() + d_W.bytes() +
+           d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
+           d_sload.bytes();
+  }
+};
+
+namespace {
+
+msfv_status check_columns(const msfv_problem* p, int count, const int* ptr, const int* cell,
+                          const double* val, Columns* out) {
+  if (count < 0 || (count > 0 && (!ptr || !cell || !val)))
+    return fail(MSFV_EINVAL, "sparse columns: null pointer or negative count");
+  Columns c;
+  c.count = count;
+  c.ptr.assign(ptr, ptr + count + 1);
+  if (c.ptr[0] != 0) return fail(MSFV_EINVAL, "sparse columns: ptr[0] must be 0");
+  for (int j = 0; j < count; ++j)
+    if (c.ptr[j + 1] < c.ptr[j]) return fail(MSFV_EINVAL, "sparse columns: ptr not monotone");
+  const int nnz = c.ptr[count];
+  c.cell.assign(cell, cell + nnz);
+  c.val.assign(val, val + nnz);
+  for (int e = 0; e < nnz; ++e) {
+    if (c.cell[e] < 0 || c.cell[e] >= p->plan.ncell)
+      return fail(MSFV_EINVAL, "sparse columns: cell index out of range");
+    if (!std::isfinite(c.val[e])) return fail(MSFV_EINVAL, "sparse columns: non-finite value");
+  }
+  *out = std::move(c);
+  return MSFV_OK;
+}
+
+// Electrode bookkeeping: direct adjoint loads, coarse right-hand-side
+// gathers and per-entity electrode lists.
+msfv_status build_electrodes(msfv_problem* p) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const int ns = p->src.count, nr = p->rec.count;
+  const int64_t nc = P.ncoarse;
+
+  // coarse right-hand side of the forward: slot (j, vid) <- sum q * S_k[cell, vid]
+  {
+    std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> slots;
+    for (int j = 0; j < ns; ++j)
+      for (int e = p->src.ptr[j]; e < p->src.ptr[j + 1]; ++e) {
+        const int cell = p->src.cell[e];
+        for (int q = P.prow[cell]; q < P.prow[cell + 1]; ++q)
+          slots[{j, P.pcol[q]}].emplace_back(q, p->src.val[e]);
+      }
+    std::vector<int> dst, ptr{0}, pidx;
+    std::vector<double> w;
+    for (auto& kv : slots) {
+      dst.push_back(int(kv.first.first * nc + kv.first.second));
+      for (auto& ent : kv.second) {
+        pidx.push_back(ent.first);
+        w.push_back(ent.second);
+      }
+      ptr.push_back(int(pidx.size()));
+    }
+    p->nsrc_slot = int(dst.size());
+    HIP_OK(p->d_src_dst.upload(dst, s));
+    HIP_OK(p->d_src_ptr.upload(ptr, s));
+    HIP_OK(p->d_src_pidx.upload(pidx, s));
+    HIP_OK(p->d_src_w.upload(w, s));
+  }
+  // coarse right-hand side of the adjoint: slot vid <- sum_i v_ij * rval * S_k[cell, vid]
+  {
+    std::map<int, std::vector<std::tuple<int, double, int>>> slots;
+    for (int i = 0; i < nr; ++i)
+      for (int e = p->rec.ptr[i]; e < p->rec.ptr[i + 1]; ++e) {
+        const int cell = p->rec.cell[e];
+        for (int q = P.prow[cell]; q < P.prow[cell + 1]; ++q)
+          slots[P.pcol[q]].emplace_back(q, p->rec.val[e], i);
+      }
+    std::vector<int> dst, ptr{0}, pidx, col;
+    std::vector<double> w;
+    for (auto& kv : slots) {
+      dst.push_back(kv.first);
+      for (auto& ent : kv.second) {
+        pidx.push_back(std::get<0>(ent));
+        w.push_back(std::get<1>(ent));
+        col.push_back(std::get<2>(ent));
+      }
+      ptr.push_back(int(pidx.size()));
+    }
+    p->nrec_slot = int(dst.size());
+    HIP_OK(p->d_rec_dst.upload(dst, s));
+    HIP_OK(p->d_rec_ptr.upload(ptr, s));
+    HIP_OK(p->d_rec_pidx.upload(pidx, s));
+    HIP_OK(p->d_rec_col.upload(col, s));
+    HIP_OK(p->d_rec_w.upload(w, s));
+  }
+  // electrodes: unique source/receiver cells that belong to an entity
+  std::map<int, std::pair<std::vector<std::pair<int, double>>, std::vector<std::pair<int, double>>>> el;
+  for (int i = 0; i < nr; ++i)
+    for (int e = p->rec.ptr[i]; e < p->rec.ptr[i + 1]; ++e) el[p->rec.cell[e]].first.emplace_back(i, p->rec.val[e]);
+  for (int j = 0; j < ns; ++j)
+    for (int e = p->src.ptr[j]; e < p->src.ptr[j + 1]; ++e) el[p->src.cell[e]].second.emplace_back(j, p->src.val[e]);
+  std::vector<int> ecell, erptr{0}, eridx, esptr{0}, esidx;
+  std::vector<double> erw, esw;
+  // per entity (kind, index) -> list of (electrode, own-cell index)
+  std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> per_ent;
+  for (auto& kv : el) {
+    int kind, idx;
+    P.entity_of_cell(kv.first, &kind, &idx);
+    if (kind == 0) continue;  // vertex cells: basis values do not depend on m
+    const msfv::EntDesc* E = P.ent(kind, idx);
+    const int cell = kv.first;
+    const int x = cell % P.n[0], y = (cell / P.n[0]) % P.n[1], z = cell / (P.n[0] * P.n[1]);
+    const int u = (x - E->ulo[0]) + E->uext[0] * ((y - E->ulo[1]) + E->uext[1] * (z - E->ulo[2]));
+    const int eid = int(ecell.size());
+    per_ent[{kind, idx}].emplace_back(eid, u);
+    ecell.push_back(cell);
+    for (auto& r : kv.second.first) {
+      eridx.push_back(r.first);
+      erw.push_back(r.second);
+    }
+    erptr.push_back(int(eridx.size()));
+    for (auto& q : kv.second.second) {
+      esidx.push_back(q.first);
+      esw.push_back(q.second);
+    }
+    esptr.push_back(int(esidx.size()));
+  }
+  p->nelec = int(ecell.size());
+  std::vector<int> eidx, eloc;
+  for (auto* list : {&p->plan.edges, &p->plan.faces, &p->plan.blocks})
+    for (auto& E : *list) E.eptr0 = E.eptr1 = 0;
+  for (auto& kv : per_ent) {
+    msfv::EntDesc* E = const_cast<msfv::EntDesc*>(P.ent(kv.first.first, kv.first.second));
+    E->eptr0 = int(eidx.size());
+    for (auto& q : kv.second) {
+      eidx.push_back(q.first);
+      eloc.push_back(q.second);
+    }
+    E->eptr1 = int(eidx.size());
+  }
+  if (eidx.empty()) {
+    eidx.push_back(0);
+    eloc.push_back(-1);
+  }
+  HIP_OK(p->d_ecell.upload(ecell, s));
+  HIP_OK(p->d_erptr.upload(erptr, s));
+  HIP_OK(p->d_eridx.upload(eridx.empty() ? std::vector<int>{0} : eridx, s));
+  HIP_OK(p->d_erw.upload(erw.empty() ? std::vector<double>{0.0} : erw, s));
+  HIP_OK(p->d_esptr.upload(esptr, s));
+  HIP_OK(p->d_esidx.upload(esidx.empty() ? std::vector<int>{0} : esidx, s));
+  HIP_OK(p->d_esw.upload(esw.empty() ? std::vector<double>{0.0} : esw, s));
+  HIP_OK(p->d_eidx.upload(eidx, s));
+  HIP_OK(p->d_eloc.upload(eloc, s));
+  HIP_OK(p->d_sload.alloc(size_t(std::max(1, p->nelec)) * 8));
+  HIP_OK(p->d_edges.upload(p->plan.edges, s));
+  HIP_OK(p->d_faces.upload(p->plan.faces, s));
+  HIP_OK(p->d_blocks.upload(p->plan.blocks, s));
+  // receivers for the data gather
+  HIP_OK(p->d_rptr.upload(p->rec.ptr, s));
+  HIP_OK(p->d_rcell.upload(p->rec.cell.empty() ? std::vector<int>{0} : p->rec.cell, s));
+  HIP_OK(p->d_rval.upload(p->rec.val.empty() ? std::vector<double>{0.0} : p->rec.val, s));
+  // coarse vectors
+  const size_t ncs = size_t(nc) * std::max(1, ns);
+  HIP_OK(p->d_b.alloc(ncs));
+  HIP_OK(p->d_t.alloc(ncs));
+  HIP_OK(p->d_lam.alloc(ncs));
+  HIP_OK(p->d_D.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
+  HIP_OK(p->d_v.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
+  HIP_OK(hipStreamSynchronize(s));  // host vectors above are temporaries
+  p->electrodes_ready = true;
+  return MSFV_OK;
+}
+
+msfv::LocalParams base_params(msfv_problem* p) {
+  msfv::LocalParams lp;
+  lp.g = p->g;
+  lp.m = p->d_m.ptr;
+  lp.prow = p->d_prow.ptr;
+  lp.pcol = p->d_pcol.ptr;
+  lp.pval = p->d_pval.ptr;
+  lp.kent = p->d_kent.ptr;
+  lp.rtol = p->cfg.local_rtol;
+  lp.maxit = p->cfg.local_maxit;
+  lp.status = p->d_status.ptr;
+  lp.sig_cap = p->plan.max_closure;
+  lp.t = p->d_t.ptr;
+  lp.lam = p->d_lam.ptr;
+  lp.ncoarse = int(p->plan.ncoarse);
+  lp.ns = p->src.count;
+  lp.inbuf = p->d_inbuf.ptr;
+  lp.outbuf = p->d_inbuf.ptr;
+  lp.eidx = p->d_eidx.ptr;
+  lp.eloc = p->d_eloc.ptr;
+  lp.sload = p->d_sload.ptr;
+  lp.W = p->d_W.ptr;
+  return lp;
+}
+
+msfv_status ensure_ready(msfv_problem* p) {
+  if (p->src.count <= 0) return fail(MSFV_ESTATE, "no sources set");
+  if (p->rec.count <= 0) return fail(MSFV_ESTATE, "no receivers set");
+  if (!p->electrodes_ready) return build_electrodes(p);
+  return MSFV_OK;
+}
+
+msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double* u_out) {
+  msfv_status st = ensure_ready(p);
+  if (st != MSFV_OK) return st;
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
+  HIP_OK(hipMemsetAsync(p->d_status.ptr, 0, sizeof(int) * msfv::kStCount, s));
+  HIP_OK(hipMemcpyAsync(p->d_m.ptr, m, sizeof(double) * P.ncell, hipMemcpyDeviceToDevice, s));
+  HIP_OK(msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
+
+  msfv::LocalParams lp = base_params(p);
+  lp.ents = p->d_edges.ptr;
+  lp.nent = int(P.edges.size());
+  HIP_OK(msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
+
+  lp = base_params(p);
+  lp.ents = p->d_faces.ptr;
+  lp.nent = int(P.faces.size());
+  lp.nu_cap = P.max_nu_face;
+  lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
+  HIP_OK(msfv::launch_local_fwd(lp, 0, s));
+
+  if (P.dim == 3) {
+    lp = base_params(p);
+    lp.ents = p->d_blocks.ptr;
+    lp.nent = int(P.blocks.size());
+    lp.nu_cap = P.max_nu_block;
+    HIP_OK(msfv::launch_local_fwd(lp, 0, s));
+  }
+  HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kent.ptr, p->d_kval.ptr,
+                                int(P.kcol.size()), s));
+  const int ns = p->src.count, nr = p->rec.count;
+  const int nc = int(P.ncoarse);
+  HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
+                                   p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
+                                   p->nsrc_slot, 1, nc, s));
+  HIP_OK(msfv::launch_coarse_pcg(p->d_krow.ptr, p->d_kcol.ptr, p->d_kval.ptr, p->d_b.ptr, p->d_t.ptr,
+                                 nc, ns, p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr,
+                                 nullptr, s));
+  HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
+                           p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
+  if (u_out)
+    HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns,
+                                P.ncell, u_out, s));
+  p->have_forward = true;
+  return MSFV_OK;
+}
+
+msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
+  if (!p->have_forward) return fail(MSFV_ESTATE, "msfv_jtv called before msfv_forward");
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
+  const int ns = p->src.count, nr = p->rec.count;
+  const int nc = int(P.ncoarse);
+  HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
+                                   p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
+                                   p->nrec_slot, ns, nc, s));
+  HIP_OK(msfv::launch_coarse_pcg(p->d_krow.ptr, p->d_kcol.ptr, p->d_kval.ptr, p->d_b.ptr,
+                                 p->d_lam.ptr, nc, ns, p->cfg.coarse_rtol, p->cfg.coarse_maxit,
+                                 p->d_status.ptr, nullptr, s));
+  HIP_OK(msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
+                            p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
+                            p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
+  msfv::LocalParams lp;
+  if (P.dim == 3) {
+    lp = base_params(p);
+    lp.ents = p->d_blocks.ptr;
+    lp.nent = int(P.blocks.size());
+    lp.nu_cap = P.max_nu_block;
+    lp.recv = p->d_faces.ptr;
+    lp.push = lagrange ? 0 : 1;
+    lp.solve_adj = 1;
+    HIP_OK(msfv::launch_local_adj(lp, 0, s));
+  }
+  lp = base_params(p);
+  lp.ents = p->d_faces.ptr;
+  lp.nent = int(P.faces.size());
+  lp.nu_cap = P.max_nu_face;
+  lp.recv = p->d_edges.ptr;
+  lp.push = lagrange ? 0 : 1;
+  lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
+  HIP_OK(msfv::launch_local_adj(lp, 0, s));
+
+  lp = base_params(p);
+  lp.ents = p->d_edges.ptr;
+  lp.nent = int(P.edges.size());
+  HIP_OK(msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
+  HIP_OK(msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
+  return MSFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* msfv_status_string(msfv_status s) {
+  switch (s) {
+    case MSFV_OK: return "ok";
+    case MSFV_EINVAL: return "invalid argument";
+    case MSFV_ENOMEM: return "out of memory";
+    case MSFV_ENOCONV: return "iteration cap reached";
+    case MSFV_ENONFINITE: return "non-finite model";
+    case MSFV_EDEVICE: return "device error";
+    case MSFV_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* msfv_last_error(void) { return g_last_error.c_str(); }
+
+msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem** out) {
+  if (!cfg || !out) return fail(MSFV_EINVAL, "null argument");
+  *out = nullptr;
+  msfv_problem* p = new (std::nothrow) msfv_problem();
+  if (!p) return fail(MSFV_ENOMEM, "host allocation failed");
+  p->cfg = *cfg;
+  if (p->cfg.bc_mode != MSFV_BC_REDUCED && p->cfg.bc_mode != MSFV_BC_LAGRANGE) {
+    delete p;
+    return fail(MSFV_EINVAL, "bc_mode must be MSFV_BC_REDUCED or MSFV_BC_LAGRANGE");
+  }
+  if (p->cfg.local_rtol <= 0) p->cfg.local_rtol = 1e-13;
+  if (p->cfg.local_maxit <= 0) p->cfg.local_maxit = 1000;
+  if (p->cfg.coarse_rtol <= 0) p->cfg.coarse_rtol = 1e-13;
+  if (p->cfg.coarse_maxit <= 0) p->cfg.coarse_maxit = 20000;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  std::string err = p->plan.build(cfg->dim, cfg->n, cfg->r);
+  if (!err.empty()) {
+    delete p;
+    return fail(MSFV_EINVAL, err);
+  }
+  const msfv::Plan& P = p->plan;
+  if (P.ncoarse > 16384) {
+    delete p;
+    return fail(MSFV_EINVAL, "coarse grid larger than 16384 vertices is not supported");
+  }
+  for (int k = 0; k < 3; ++k) p->g.n[k] = P.n[k];
+  p->g.s1 = P.stride[1];
+  p->g.s2 = P.stride[2];
+  hipStream_t s = p->stream;
+  auto cleanup = [&](msfv_status st) {
+    delete p;
+    return st;
+  };
+#define HIP_OR_CLEAN(expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return cleanup(fail(e_ == hipErrorOutOfMemory ? MSFV_ENOMEM : MSFV_EDEVICE,              \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)));                 \
+  } while (0)
+  HIP_OR_CLEAN(p->d_edges.upload(P.edges, s));
+  HIP_OR_CLEAN(p->d_faces.upload(P.faces, s));
+  HIP_OR_CLEAN(p->d_blocks.upload(P.blocks, s));
+  HIP_OR_CLEAN(p->d_prow.upload(P.prow, s));
+  HIP_OR_CLEAN(p->d_pcol.upload(P.pcol, s));
+  HIP_OR_CLEAN(p->d_krow.upload(P.krow, s));
+  HIP_OR_CLEAN(p->d_kcol.upload(P.kcol, s));
+  HIP_OR_CLEAN(p->d_kcptr.upload(P.kcptr, s));
+  HIP_OR_CLEAN(p->d_kcidx.upload(P.kcidx, s));
+  HIP_OR_CLEAN(p->d_pval.alloc(P.pcol.size()));
+  HIP_OR_CLEAN(p->d_kval.alloc(std::max<size_t>(1, P.kcol.size())));
+  HIP_OR_CLEAN(p->d_kent.alloc(std::max<int64_t>(1, P.kent_size)));
+  HIP_OR_CLEAN(p->d_inbuf.alloc(std::max<int64_t>(1, P.inbuf_size)));
+  HIP_OR_CLEAN(p->d_W.alloc(size_t(3) * P.ncell));
+  HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
+  HIP_OR_CLEAN(p->d_status.alloc(msfv::kStCount));
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_pval.ptr, 0, p->d_pval.bytes(), s));
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_inbuf.ptr, 0, p->d_inbuf.bytes(), s));
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_W.ptr, 0, p->d_W.bytes(), s));
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_status.ptr, 0, p->d_status.bytes(), s));
+  std::vector<int> vrows;
+  for (int K = 0; K < P.ncv[2]; ++K)
+    for (int J = 0; J < P.ncv[1]; ++J)
+      for (int I = 0; I < P.ncv[0]; ++I)
+        vrows.push_back(P.prow[P.ax[0].v[I] + int64_t(P.ax[1].v[J]) * P.stride[1] +
+                               int64_t(P.ax[2].v[K]) * P.stride[2]]);
+  HIP_OR_CLEAN(p->d_vrows.upload(vrows, s));
+  HIP_OR_CLEAN(msfv::launch_set_ones(p->d_vrows.ptr, int(vrows.size()), p->d_pval.ptr, s));
+  HIP_OR_CLEAN(hipStreamSynchronize(s));
+#undef HIP_OR_CLEAN
+  *out = p;
+  return MSFV_OK;
+}
+
+void msfv_destroy(msfv_problem* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  delete p;
+}
+
+msfv_status msfv_set_sources(msfv_problem* p, int ns, const int* ptr, const int* cell, const double* val) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  Columns c;
+  msfv_status st = check_columns(p, ns, ptr, cell, val, &c);
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipStreamSynchronize(p->stream));
+  p->src = std::move(c);
+  p->electrodes_ready = false;
+  p->have_forward = false;
+  return MSFV_OK;
+}
+
+msfv_status msfv_set_receivers(msfv_problem* p, int nr, const int* ptr, const int* cell, const double* val) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  Columns c;
+  msfv_status st = check_columns(p, nr, ptr, cell, val, &c);
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipStreamSynchronize(p->stream));
+  p->rec = std::move(c);
+  p->electrodes_ready = false;
+  p->have_forward = false;
+  return MSFV_OK;
+}
+
+msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double* u_out) {
+  if (!p || !m || !d_out) return fail(MSFV_EINVAL, "null argument");
+  return forward_impl(p, m, d_out, u_out);
+}
+
+msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out) {
+  if (!p || !v || !g_out) return fail(MSFV_EINVAL, "null argument");
+  return jtv_impl(p, v, g_out);
+}
+
+msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_obs, double* phi_out,
+                             double* g_out) {
+  if (!p || !m || !d_obs || !phi_out || !g_out) return fail(MSFV_EINVAL, "null argument");
+  msfv_status st = ensure_ready(p);
+  if (st != MSFV_OK) return st;
+  st = forward_impl(p, m, p->d_D.ptr, nullptr);
+  if (st != MSFV_OK) return st;
+  const long long n = (long long)p->rec.count * p->src.count;
+  HIP_OK(msfv::launch_residual(p->d_D.ptr, d_obs, p->d_v.ptr, n, phi_out, p->stream));
+  return jtv_impl(p, p->d_v.ptr, g_out);
+}
+
+msfv_status msfv_sync(msfv_problem* p) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  int st[msfv::kStCount];
+  HIP_OK(hipMemcpy(st, p->d_status.ptr, sizeof st, hipMemcpyDeviceToHost));
+  if (st[msfv::kStNonfinite]) return fail(MSFV_ENONFINITE, "m contains NaN or Inf");
+  if (st[msfv::kStLocalNoconv] || st[msfv::kStCoarseNoconv])
+    return fail(MSFV_ENOCONV, "an iteration reached its cap");
+  return MSFV_OK;
+}
+
+msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out) {
+  if (!p || !out) return fail(MSFV_EINVAL, "null argument");
+  const msfv::Plan& P = p->plan;
+  out->ncell = P.ncell;
+  out->ncoarse = P.ncoarse;
+  out->nnz_p = (long long)P.pcol.size();
+  out->nnz_k = (long long)P.kcol.size();
+  out->nsrc = p->src.count;
+  out->nrec = p->rec.count;
+  out->nblock = int(P.blocks.size());
+  out->nface = P.dim == 3 ? int(P.faces.size()) : 0;
+  out->nedge = int(P.edges.size());
+  out->workspace_bytes = (long long)p->workspace_bytes();
+  return MSFV_OK;
+}
+
+msfv_status msfv_get_prolongation(msfv_problem* p, int* row_ptr, int* col, double* val) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  const msfv::Plan& P = p->plan;
+  if (row_ptr) std::memcpy(row_ptr, P.prow.data(), P.prow.size() * sizeof(int));
+  if (col) std::memcpy(col, P.pcol.data(), P.pcol.size() * sizeof(int));
+  if (val) HIP_OK(hipMemcpy(val, p->d_pval.ptr, P.pcol.size() * sizeof(double), hipMemcpyDeviceToHost));
+  return MSFV_OK;
+}
+
+msfv_status msfv_get_coarse(msfv_problem* p, int* row_ptr, int* col, double* val, double* t_out) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  const msfv::Plan& P = p->plan;
+  if (row_ptr) std::memcpy(row_ptr, P.krow.data(), P.krow.size() * sizeof(int));
+  if (col) std::memcpy(col, P.kcol.data(), P.kcol.size() * sizeof(int));
+  if (val) HIP_OK(hipMemcpy(val, p->d_kval.ptr, P.kcol.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (t_out && p->d_t.ptr)
+    HIP_OK(hipMemcpy(t_out, p->d_t.ptr, size_t(P.ncoarse) * p->src.count * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  return MSFV_OK;
+}
+
+msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out) {
+  if (!p || !out) return fail(MSFV_EINVAL, "null argument");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  int st[msfv::kStCount];
+  HIP_OK(hipMemcpy(st, p->d_status.ptr, sizeof st, hipMemcpyDeviceToHost));
+  out->local_max_it = st[msfv::kStLocalMaxIt];
+  out->local_noconv = st[msfv::kStLocalNoconv];
+  out->coarse_max_it = st[msfv::kStCoarseMaxIt];
+  out->coarse_noconv = st[msfv::kStCoarseNoconv];
+  out->nonfinite = st[msfv::kStNonfinite];
+  return MSFV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1168 @@
+// gfx950 kernels of the adaptive MSFV path.
+//
+// Forward (Sec. 3.2, eq. multiscaleBasis_step3; eq. reducedPDE; eq. fwdProbRed)
+//   k_edge_fwd     one thread per edge entity: the 1-D reduced problem has the
+//                  closed form "fraction of cumulative resistance"; also its
+//                  energy block.
+//   k_local_fwd    one workgroup per face (2 open axes) or dual block (3 open
+//                  axes): conductivities of the closed box in LDS, Jacobi-PCG
+//                  on the reduced operator for all corners at once (search
+//                  directions in LDS, wavefront-shuffle dot products), values
+//                  written into the CSR rows of S_k, and the entity's energy
+//                  block sum_f T_f dphi_f dphi_f^T over the fluxes it touches.
+//   k_kassemble    A_k = S_k^T A S_k as a deterministic gather of energy blocks.
+//   k_coarse_pcg   one workgroup per source column: Jacobi-PCG on A_k with
+//                  coarse vertex 0 fixed (the potential is fixed at one point).
+//   gathers        S_k^T q, D = Rx^T S_k t, u = S_k t.
+// Adjoint (Sec. 4.3 eq. sensred and Sec. 4.5, transposed and source-reduced)
+//   With lambda_j = A_k^{-1} S_k^T Rx v_j and M = sum_j t_j lambda_j^T, the
+//   gradient is sum over basis functions c of the reverse sweep of s_c with
+//   load z_c = sum_j (t_jc Rx v_j + lambda_jc q_j) - A y_c,
+//   y_c = sum_c' (M + M^T)_{c'c} s_c', plus the flux-derivative term
+//   -sum_f dT_f/dm dphi_f^T M dphi_f.  Entities are swept in decreasing
+//   dimension; each solves A^E_EE mu_c = z_c|E for its corners, adds
+//   -dT_f (dmu_c)(dphi_c) to the flux weight W_f of every flux it touches,
+//   and pushes T_f (mu_c + dy_c) onto its Dirichlet neighbours, which belong
+//   to the entity of next lower dimension.  k_gfinal turns flux weights into
+//   g_i = sum_{f ni i} dT_f/dm_i W_f.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace msfv {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+// d/dm_a of the harmonic transmissibility for sigma = exp(m)
+__device__ __forceinline__ double dharm(double a, double b) {
+  double s = a + b;
+  return 2.0 * a * b * b / (s * s);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum NV values over the workgroup; every thread receives the totals.  The
+// butterfly is commutative-exact, so all lanes agree bit for bit, and waves
+// are summed in a fixed order: results are deterministic.
+template <int NW, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], int nv, double* red) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i < nv) v[i] = wave_sum(v[i]);
+  if (NW == 1) return;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) red[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if (i < nv) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w * NV + i];
+      v[i] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double p_lookup(const int* prow, const int* pcol, const double* pval,
+                                           int gid, int vid) {
+  const int a = prow[gid], b = prow[gid + 1];
+  double v = 0.0;
+  for (int e = a; e < b; ++e)
+    if (pcol[e] == vid) v = pval[e];
+  return v;
+}
+
+struct CellGeo {
+  int u;      // own-cell index, -1 for an unused slot
+  int gid;    // global cell id
+  int gc[3];  // global coordinates
+  int fmask;  // bit d = 2k+plus: a flux of the reduced operator exists in direction d
+  int umask;  // bit d: that neighbour is an own cell (else a Dirichlet cell)
+  double T[6];
+  double diag;
+  double dinv;
+};
+
+__device__ __forceinline__ int gstride_of(const GridInfo& g, int k) {
+  return k == 0 ? 1 : (k == 1 ? g.s1 : g.s2);
+}
+
+__device__ __forceinline__ int ustride_of(const EntDesc& E, int k) {
+  return k == 0 ? 1 : (k == 1 ? E.uext[0] : E.uext[0] * E.uext[1]);
+}
+
+// Neighbour geometry of own cell u from the closure conductivities in LDS.
+__device__ void cell_setup(const EntDesc& E, const GridInfo& g, const double* sig, int u,
+                           CellGeo& c) {
+  c.u = u;
+  const int ux = u % E.uext[0];
+  const int t = u / E.uext[0];
+  const int uy = t % E.uext[1];
+  const int uz = t / E.uext[1];
+  c.gc[0] = E.ulo[0] + ux;
+  c.gc[1] = E.ulo[1] + uy;
+  c.gc[2] = E.ulo[2] + uz;
+  c.gid = c.gc[0] + g.s1 * c.gc[1] + g.s2 * c.gc[2];
+  const int l[3] = {c.gc[0] - E.clo[0], c.gc[1] - E.clo[1], c.gc[2] - E.clo[2]};
+  const int cs[3] = {1, E.cext[0], E.cext[0] * E.cext[1]};
+  const int uc[3] = {ux, uy, uz};
+  const int lc = l[0] + cs[1] * l[1] + cs[2] * l[2];
+  const double s0 = sig[lc];
+  double diag = 0.0;
+  c.fmask = 0;
+  c.umask = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      const int d = 2 * k + pl;
+      c.T[d] = 0.0;
+      if (!((E.open_mask >> k) & 1)) continue;
+      const int step = pl ? 1 : -1;
+      const int lk = l[k] + step;
+      if (lk < 0 || lk >= E.cext[k]) continue;  // outside the closure = outside the domain
+      const double tt = harm(s0, sig[lc + step * cs[k]]);
+      c.T[d] = tt;
+      diag += tt;
+      c.fmask |= 1 << d;
+      const int uk = uc[k] + step;
+      if (uk >= 0 && uk < E.uext[k]) c.umask |= 1 << d;
+    }
+  }
+  c.diag = diag;
+  c.dinv = diag > 0.0 ? 1.0 / diag : 0.0;
+}
+
+__device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[3], int ci) {
+  double v = 1.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (!((E.bounded_mask >> k) & 1)) continue;
+    const double lo = E.clo[k], hi = E.clo[k] + E.cext[k] - 1;
+    const double x = gc[k];
+    const bool upper = (E.cbits >> (3 * ci + k)) & 1;
+    v *= upper ? (x - lo) / (hi - lo) : (hi - x) / (hi - lo);
+  }
+  return v;
+}
+
+// Jacobi-PCG on A^E_EE for ncp right-hand sides at once.  Search directions
+// live in LDS (pb[c*nu + u]); x, r and p for the thread's own cells live in
+// registers.  Stops when ||r_c|| <= rtol ||b_c|| for every column.
+template <int BLOCK, int CPT, int NCP>
+__device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], int ncp,
+                         const double (&b)[CPT][NCP], double (&x)[CPT][NCP], double* pb,
+                         double* redA, double* redB, double tol2, int maxit, bool* ok) {
+  constexpr int NW = BLOCK / kWave;
+  const int nu = E.nu;
+  double r[CPT][NCP], pv[CPT][NCP];
+  double sums[2 * NCP];
+#pragma unroll
+  for (int c = 0; c < 2 * NCP; ++c) sums[c] = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+      x[j][c] = 0.0;
+      r[j][c] = b[j][c];
+      pv[j][c] = r[j][c] * cg[j].dinv;
+      if (cg[j].u >= 0 && c < ncp) {
+        sums[c] += b[j][c] * b[j][c];
+        sums[NCP + c] += r[j][c] * pv[j][c];
+        pb[c * nu + cg[j].u] = pv[j][c];
+      }
+    }
+  }
+  block_sum<NW, 2 * NCP>(sums, 2 * NCP, redA);
+  double bb[NCP], rz[NCP];
+  bool done = true;
+#pragma unroll
+  for (int c = 0; c < NCP; ++c) {
+    bb[c] = sums[c];
+    rz[c] = sums[NCP + c];
+    if (c < ncp && bb[c] > 0.0) done = false;
+  }
+  __syncthreads();
+  int it = 0;
+  *ok = true;
+  while (!done) {
+    if (it >= maxit) {
+      *ok = false;
+      break;
+    }
+    ++it;
+    double ap[CPT][NCP];
+    double pq[NCP];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) pq[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (cg[j].u < 0) continue;
+#pragma unroll
+      for (int c = 0; c < NCP; ++c) ap[j][c] = cg[j].diag * pv[j][c];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        if (!((cg[j].umask >> d) & 1)) continue;
+        const int k = d >> 1;
+        const int nb = cg[j].u + ((d & 1) ? ustride_of(E, k) : -ustride_of(E, k));
+        const double tt = cg[j].T[d];
+#pragma unroll
+        for (int c = 0; c < NCP; ++c)
+          if (c < ncp) ap[j][c] -= tt * pb[c * nu + nb];
+      }
+#pragma unroll
+      for (int c = 0; c < NCP; ++c)
+        if (c < ncp) pq[c] += pv[j][c] * ap[j][c];
+    }
+    block_sum<NW, NCP>(pq, ncp, redA);
+    double alpha[NCP];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) alpha[c] = (c < ncp && pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 2 * NCP; ++c) sums[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (cg[j].u < 0) continue;
+#pragma unroll
+      for (int c = 0; c < NCP; ++c) {
+        if (c >= ncp) continue;
+        x[j][c] += alpha[c] * pv[j][c];
+        r[j][c] -= alpha[c] * ap[j][c];
+        const double z = r[j][c] * cg[j].dinv;
+        sums[c] += r[j][c] * r[j][c];
+        sums[NCP + c] += r[j][c] * z;
+      }
+    }
+    block_sum<NW, 2 * NCP>(sums, 2 * NCP, redB);
+    bool conv = true;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+      if (c >= ncp) continue;
+      if (!(sums[c] <= tol2 * bb[c])) conv = false;
+      if (sums[c] != sums[c]) bad = true;
+    }
+    if (conv) break;
+    if (bad) {
+      *ok = false;
+      break;
+    }
+    double beta[NCP];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+      beta[c] = (c < ncp && rz[c] != 0.0) ? sums[NCP + c] / rz[c] : 0.0;
+      rz[c] = sums[NCP + c];
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (cg[j].u < 0) continue;
+#pragma unroll
+      for (int c = 0; c < NCP; ++c) {
+        if (c >= ncp) continue;
+        pv[j][c] = r[j][c] * cg[j].dinv + beta[c] * pv[j][c];
+        pb[c * nu + cg[j].u] = pv[j][c];
+      }
+    }
+    __syncthreads();
+  }
+  return it;
+}
+
+template <int BLOCK, int CPT>
+__device__ void load_closure_sigma(const EntDesc& E, const GridInfo& g, const double* m,
+                                   double* sig) {
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  for (int i = threadIdx.x; i < ncl; i += BLOCK) {
+    const int lx = i % E.cext[0];
+    const int t = i / E.cext[0];
+    const int ly = t % E.cext[1];
+    const int lz = t / E.cext[1];
+    const int gid = (E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz);
+    sig[i] = exp(m[gid]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward: faces and dual blocks
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT, int NCP>
+__global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
+  extern __shared__ double lds[];
+  constexpr int NW = BLOCK / kWave;
+  const EntDesc E = a.ents[blockIdx.x];
+  double* sig = lds;
+  double* pb = sig + a.sig_cap;
+  double* redA = pb + NCP * a.nu_cap;
+  double* redB = redA + NW * 40;
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  __syncthreads();
+  CellGeo cg[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int u = threadIdx.x + j * BLOCK;
+    if (u < E.nu)
+      cell_setup(E, a.g, sig, u, cg[j]);
+    else
+      cg[j].u = -1;
+  }
+  const double tol2 = a.rtol * a.rtol;
+  int itmax = 0;
+  bool all_ok = true;
+  for (int c0 = 0; c0 < E.nc; c0 += NCP) {
+    const int ncp = min(NCP, E.nc - c0);
+    double x[CPT][NCP];
+    if (a.prescribe) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int c = 0; c < NCP; ++c)
+          x[j][c] = (cg[j].u >= 0 && c < ncp) ? lagrange_value(E, cg[j].gc, c0 + c) : 0.0;
+    } else {
+      double b[CPT][NCP];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) b[j][c] = 0.0;
+        if (cg[j].u < 0) continue;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          if (!((cg[j].fmask >> d) & 1) || ((cg[j].umask >> d) & 1)) continue;
+          const int k = d >> 1;
+          const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+#pragma unroll
+          for (int c = 0; c < NCP; ++c)
+            if (c < ncp) b[j][c] += cg[j].T[d] * p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c0 + c]);
+        }
+      }
+      __syncthreads();  // previous pass finished with the LDS buffers
+      bool ok = true;
+      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      itmax = max(itmax, it);
+      all_ok = all_ok && ok;
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (cg[j].u < 0) continue;
+      const int base = a.prow[cg[j].gid] + c0;
+#pragma unroll
+      for (int c = 0; c < NCP; ++c)
+        if (c < ncp) a.pval[base + c] = x[j][c];
+    }
+  }
+  if (threadIdx.x == 0 && !a.prescribe) {
+    atomicMax(a.status + kStLocalMaxIt, itmax);
+    if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
+  }
+  __syncthreads();  // S_k rows of this entity are visible to the workgroup
+
+  // energy block: K_E = sum over touched fluxes T_f dphi_f dphi_f^T
+  const int nc = E.nc;
+  double kacc[36];
+#pragma unroll
+  for (int i = 0; i < 36; ++i) kacc[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    if (cg[j].u < 0) continue;
+    double pu[8];
+    const int base = a.prow[cg[j].gid];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pu[c] = c < nc ? a.pval[base + c] : 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!((cg[j].fmask >> d) & 1)) continue;
+      const bool own = (cg[j].umask >> d) & 1;
+      if (!(d & 1) && own) continue;  // counted from the lower own cell
+      const int k = d >> 1;
+      const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+      double dp[8];
+      const int nbase = a.prow[ng];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c >= nc) {
+          dp[c] = 0.0;
+          continue;
+        }
+        const double pn = own ? a.pval[nbase + c] : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]);
+        dp[c] = pu[c] - pn;
+      }
+      const double tt = cg[j].T[d];
+      int q = 0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int c2 = c; c2 < 8; ++c2) {
+          kacc[q] += tt * dp[c] * dp[c2];
+          ++q;
+        }
+    }
+  }
+  __syncthreads();
+  block_sum<NW, 36>(kacc, 36, redA);
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int c = 0; c < 8; ++c)
+      for (int c2 = c; c2 < 8; ++c2) {
+        if (c < nc && c2 < nc) {
+          a.kent[E.kbase + c * nc + c2] = kacc[q];
+          a.kent[E.kbase + c2 * nc + c] = kacc[q];
+        }
+        ++q;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: dual blocks and faces
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT, int NCP>
+__global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
+  extern __shared__ double lds[];
+  constexpr int NW = BLOCK / kWave;
+  const EntDesc E = a.ents[blockIdx.x];
+  double* sig = lds;
+  double* pb = sig + a.sig_cap;
+  double* redA = pb + NCP * a.nu_cap;
+  double* redB = redA + NW * 40;
+  double* Mm = redB + NW * 40;  // 64
+  double* Sm = Mm + 64;         // 64
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  const int nc = E.nc;
+  if (threadIdx.x < nc * nc) {
+    const int c = threadIdx.x / nc, c2 = threadIdx.x % nc;
+    double s = 0.0;
+    for (int j = 0; j < a.ns; ++j)
+      s += a.t[size_t(j) * a.ncoarse + E.vid[c]] * a.lam[size_t(j) * a.ncoarse + E.vid[c2]];
+    Mm[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nc * nc) {
+    const int c = threadIdx.x / nc, c2 = threadIdx.x % nc;
+    Sm[threadIdx.x] = Mm[c * nc + c2] + Mm[c2 * nc + c];
+  }
+  CellGeo cg[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int u = threadIdx.x + j * BLOCK;
+    if (u < E.nu)
+      cell_setup(E, a.g, sig, u, cg[j]);
+    else
+      cg[j].u = -1;
+  }
+  __syncthreads();
+
+  // loads z_c on own cells and the flux-derivative term of the touched fluxes
+  double zh[CPT][8];
+  double wf[CPT][6];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) zh[j][c] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) wf[j][d] = 0.0;
+    if (cg[j].u < 0) continue;
+    const int u = cg[j].u;
+    if (E.inbase >= 0) {
+      for (int s = 0; s < E.nslot; ++s)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c < nc) zh[j][c] += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
+    }
+    for (int e = E.eptr0; e < E.eptr1; ++e)
+      if (a.eloc[e] == u)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c < nc) zh[j][c] += a.sload[a.eidx[e] * 8 + c];
+    double pu[8];
+    const int base = a.prow[cg[j].gid];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pu[c] = c < nc ? a.pval[base + c] : 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!((cg[j].fmask >> d) & 1)) continue;
+      const bool own = (cg[j].umask >> d) & 1;
+      const int k = d >> 1;
+      const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+      double dp[8];
+      const int nbase = a.prow[ng];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        dp[c] = c < nc ? pu[c] - (own ? a.pval[nbase + c]
+                                      : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]))
+                       : 0.0;
+      const double tt = cg[j].T[d];
+      double quad = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c >= nc) continue;
+        double dy = 0.0, mq = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) {
+          if (c2 >= nc) continue;
+          dy += Sm[c2 * nc + c] * dp[c2];
+          mq += Mm[c * nc + c2] * dp[c2];
+        }
+        zh[j][c] -= tt * dy;
+        quad += dp[c] * mq;
+      }
+      if ((d & 1) || !own) wf[j][d] = -quad;
+    }
+  }
+
+  if (a.solve_adj) {
+    const double tol2 = a.rtol * a.rtol;
+    int itmax = 0;
+    bool all_ok = true;
+    for (int c0 = 0; c0 < nc; c0 += NCP) {
+      const int ncp = min(NCP, nc - c0);
+      double b[CPT][NCP], x[CPT][NCP];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) b[j][c] = (c < ncp) ? zh[j][c0 + c] : 0.0;
+      __syncthreads();
+      bool ok = true;
+      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      itmax = max(itmax, it);
+      all_ok = all_ok && ok;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+        if (cg[j].u >= 0)
+#pragma unroll
+          for (int c = 0; c < NCP; ++c)
+            if (c < ncp) pb[c * E.nu + cg[j].u] = x[j][c];
+      __syncthreads();
+      // flux weights and pushes for this pass's corners
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        if (cg[j].u < 0) continue;
+        const int base = a.prow[cg[j].gid];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          if (!((cg[j].fmask >> d) & 1)) continue;
+          const bool own = (cg[j].umask >> d) & 1;
+          const int k = d >> 1;
+          const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+          const int nb = cg[j].u + ((d & 1) ? ustride_of(E, k) : -ustride_of(E, k));
+          const int nbase = a.prow[ng];
+          double dp[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            dp[c] = c < nc ? a.pval[base + c] - (own ? a.pval[nbase + c]
+                                                     : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]))
+                           : 0.0;
+          if ((d & 1) || !own) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < NCP; ++c) {
+              if (c >= ncp) continue;
+              const double mun = own ? pb[c * E.nu + nb] : 0.0;
+              s += (x[j][c] - mun) * dp[c0 + c];
+            }
+            wf[j][d] -= s;
+          }
+          if (!own && a.push) {
+            const int te = E.side_ent[d];
+            if (te < 0) continue;
+            const EntDesc& R = a.recv[te];
+            int gc2[3] = {cg[j].gc[0], cg[j].gc[1], cg[j].gc[2]};
+            gc2[k] += (d & 1) ? 1 : -1;
+            const int ut = (gc2[0] - R.ulo[0]) + R.uext[0] * ((gc2[1] - R.ulo[1]) + R.uext[1] * (gc2[2] - R.ulo[2]));
+            const double tt = cg[j].T[d];
+#pragma unroll
+            for (int c = 0; c < NCP; ++c) {
+              if (c >= ncp) continue;
+              const int vid = E.vid[c0 + c];
+              int ct = -1;
+              for (int q = 0; q < R.nc; ++q)
+                if (R.vid[q] == vid) ct = q;
+              if (ct < 0) continue;
+              double dy = 0.0;
+#pragma unroll
+              for (int c2 = 0; c2 < 8; ++c2)
+                if (c2 < nc) dy += Sm[c2 * nc + c0 + c] * dp[c2];
+              a.outbuf[R.inbase + (E.side_slot[d] * R.nc + ct) * R.nu + ut] = tt * (x[j][c] + dy);
+            }
+          }
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      atomicMax(a.status + kStLocalMaxIt, itmax);
+      if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
+    }
+  }
+  // flux weights of the fluxes this entity owns
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    if (cg[j].u < 0) continue;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!((cg[j].fmask >> d) & 1)) continue;
+      const bool own = (cg[j].umask >> d) & 1;
+      if (!(d & 1) && own) continue;
+      const int k = d >> 1;
+      const int lower = (d & 1) ? cg[j].gid : cg[j].gid - gstride_of(a.g, k);
+      const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
+      a.W[k * N + lower] = wf[j][d];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// edges: closed-form forward, tridiagonal adjoint (one thread per edge)
+// ---------------------------------------------------------------------------
+constexpr int kMaxLine = 17;  // closure cells along an edge for r <= 16
+
+struct EdgeLine {
+  int k, len, base, st, u0;
+  double sig[kMaxLine];
+  double T[kMaxLine];
+};
+
+__device__ void edge_line(const EntDesc& E, const GridInfo& g, const double* m, EdgeLine& L) {
+  L.k = (E.open_mask & 1) ? 0 : ((E.open_mask & 2) ? 1 : 2);
+  L.len = E.cext[L.k];
+  L.base = E.clo[0] + g.s1 * E.clo[1] + g.s2 * E.clo[2];
+  L.st = gstride_of(g, L.k);
+  L.u0 = E.ulo[L.k] - E.clo[L.k];
+  for (int i = 0; i < L.len; ++i) L.sig[i] = exp(m[L.base + i * L.st]);
+  for (int i = 0; i + 1 < L.len; ++i) L.T[i] = harm(L.sig[i], L.sig[i + 1]);
+}
+
+// basis values of the edge's corners at closure position i
+__device__ __forceinline__ void edge_phi(const EntDesc& E, const EdgeLine& L, const double* cum,
+                                         int lagrange, int i, double* phi) {
+  if (E.nc == 1) {
+    phi[0] = 1.0;
+    return;
+  }
+  if (lagrange) {
+    const double h = L.len - 1;
+    phi[0] = (h - i) / h;
+    phi[1] = double(i) / h;
+  } else {
+    const double R = cum[L.len - 1];
+    phi[0] = (R - cum[i]) / R;
+    phi[1] = cum[i] / R;
+  }
+}
+
+__global__ void k_edge_fwd(LocalParams a, int lagrange) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nent) return;
+  const EntDesc E = a.ents[e];
+  EdgeLine L;
+  edge_line(E, a.g, a.m, L);
+  double cum[kMaxLine];
+  cum[0] = 0.0;
+  for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
+  for (int q = 0; q < E.nu; ++q) {
+    const int i = L.u0 + q;
+    double phi[2];
+    edge_phi(E, L, cum, lagrange, i, phi);
+    const int row = a.prow[L.base + i * L.st];
+    for (int c = 0; c < E.nc; ++c) a.pval[row + c] = phi[c];
+  }
+  double k00 = 0.0, k01 = 0.0, k11 = 0.0;
+  for (int i = 0; i + 1 < L.len; ++i) {
+    double pa[2], pb2[2];
+    edge_phi(E, L, cum, lagrange, i, pa);
+    edge_phi(E, L, cum, lagrange, i + 1, pb2);
+    if (E.nc == 1) continue;
+    const double d0 = pa[0] - pb2[0], d1 = pa[1] - pb2[1];
+    k00 += L.T[i] * d0 * d0;
+    k01 += L.T[i] * d0 * d1;
+    k11 += L.T[i] * d1 * d1;
+  }
+  if (E.nc == 1) {
+    a.kent[E.kbase] = 0.0;
+  } else {
+    a.kent[E.kbase + 0] = k00;
+    a.kent[E.kbase + 1] = k01;
+    a.kent[E.kbase + 2] = k01;
+    a.kent[E.kbase + 3] = k11;
+  }
+}
+
+__global__ void k_edge_adj(LocalParams a, int lagrange) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nent) return;
+  const EntDesc E = a.ents[e];
+  EdgeLine L;
+  edge_line(E, a.g, a.m, L);
+  const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
+  double* Wk = a.W + L.k * N;
+  if (E.nc == 1) {  // strip: s = 1 for every m, nothing depends on m
+    for (int i = 0; i + 1 < L.len; ++i) Wk[L.base + i * L.st] = 0.0;
+    return;
+  }
+  double cum[kMaxLine];
+  cum[0] = 0.0;
+  for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
+  double M[4] = {0, 0, 0, 0};
+  for (int j = 0; j < a.ns; ++j) {
+    const double t0 = a.t[size_t(j) * a.ncoarse + E.vid[0]], t1 = a.t[size_t(j) * a.ncoarse + E.vid[1]];
+    const double l0 = a.lam[size_t(j) * a.ncoarse + E.vid[0]], l1 = a.lam[size_t(j) * a.ncoarse + E.vid[1]];
+    M[0] += t0 * l0;
+    M[1] += t0 * l1;
+    M[2] += t1 * l0;
+    M[3] += t1 * l1;
+  }
+  const double S[4] = {2 * M[0], M[1] + M[2], M[1] + M[2], 2 * M[3]};
+  // loads on own cells (closure positions 1 .. len-2 for a bounded edge)
+  double z0[kMaxLine], z1[kMaxLine];
+  for (int q = 0; q < E.nu; ++q) {
+    const int i = L.u0 + q;
+    double l0 = 0.0, l1 = 0.0;
+    for (int s = 0; s < E.nslot; ++s) {
+      l0 += a.inbuf[E.inbase + (s * 2 + 0) * E.nu + q];
+      l1 += a.inbuf[E.inbase + (s * 2 + 1) * E.nu + q];
+    }
+    for (int ee = E.eptr0; ee < E.eptr1; ++ee)
+      if (a.eloc[ee] == q) {
+        l0 += a.sload[a.eidx[ee] * 8 + 0];
+        l1 += a.sload[a.eidx[ee] * 8 + 1];
+      }
+    double pu[2], pn[2];
+    edge_phi(E, L, cum, lagrange, i, pu);
+    for (int side = -1; side <= 1; side += 2) {
+      const int nbp = i + side;
+      const int f = side < 0 ? i - 1 : i;
+      edge_phi(E, L, cum, lagrange, nbp, pn);
+      const double d0 = pu[0] - pn[0], d1 = pu[1] - pn[1];
+      l0 -= L.T[f] * (S[0] * d0 + S[2] * d1);
+      l1 -= L.T[f] * (S[1] * d0 + S[3] * d1);
+    }
+    z0[i] = l0;
+    z1[i] = l1;
+  }
+  // mu = (A^E_EE)^{-1} z by the Thomas algorithm (an M-matrix, no pivoting)
+  double mu0[kMaxLine], mu1[kMaxLine];
+  for (int i = 0; i < L.len; ++i) mu0[i] = mu1[i] = 0.0;
+  if (!lagrange) {
+    double cp[kMaxLine];
+    const int i0 = L.u0, i1 = L.u0 + E.nu - 1;
+    for (int i = i0; i <= i1; ++i) {
+      const double lo = (i > 0) ? L.T[i - 1] : 0.0;
+      const double hi = (i + 1 < L.len) ? L.T[i] : 0.0;
+      const double diag = lo + hi;
+      const double sub = (i > i0) ? -lo : 0.0;
+      const double den = diag - sub * ((i > i0) ? cp[i - 1] : 0.0);
+      cp[i] = (i < i1) ? -hi / den : 0.0;
+      mu0[i] = (z0[i] - sub * ((i > i0) ? mu0[i - 1] : 0.0)) / den;
+      mu1[i] = (z1[i] - sub * ((i > i0) ? mu1[i - 1] : 0.0)) / den;
+    }
+    for (int i = i1 - 1; i >= i0; --i) {
+      mu0[i] -= cp[i] * mu0[i + 1];
+      mu1[i] -= cp[i] * mu1[i + 1];
+    }
+  }
+  for (int i = 0; i + 1 < L.len; ++i) {
+    double pa[2], pb2[2];
+    edge_phi(E, L, cum, lagrange, i, pa);
+    edge_phi(E, L, cum, lagrange, i + 1, pb2);
+    const double d0 = pa[0] - pb2[0], d1 = pa[1] - pb2[1];
+    const double quad = d0 * (M[0] * d0 + M[1] * d1) + d1 * (M[2] * d0 + M[3] * d1);
+    const double w = -((mu0[i] - mu0[i + 1]) * d0 + (mu1[i] - mu1[i + 1]) * d1) - quad;
+    Wk[L.base + i * L.st] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coarse operator, coarse solve, gathers
+// ---------------------------------------------------------------------------
+__global__ void k_check_finite(const double* m, long long n, int* status) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = m[i];
+    if (!isfinite(v)) bad = true;
+  }
+  if (bad) atomicOr(status + kStNonfinite, 1);
+}
+
+__global__ void k_set_ones(const int* idx, int n, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[idx[i]] = 1.0;
+}
+
+__global__ void k_kassemble(const int* kcptr, const int* kcidx, const double* kent, double* kval,
+                            int nnz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  double s = 0.0;
+  for (int e = kcptr[i]; e < kcptr[i + 1]; ++e) s += kent[kcidx[e]];
+  kval[i] = s;
+}
+
+template <int BLOCK, int RPT>
+__global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const int* krow, const int* kcol,
+                                                      const double* kval, const double* rhs,
+                                                      double* xout, int nc, double rtol, int maxit,
+                                                      int* status) {
+  extern __shared__ double lds[];
+  constexpr int NW = BLOCK / kWave;
+  double* p = lds;
+  double* redA = p + nc;
+  double* redB = redA + NW * 4;
+  const double* b = rhs + size_t(blockIdx.x) * nc;
+  double* xo = xout + size_t(blockIdx.x) * nc;
+  double x[RPT], r[RPT], pv[RPT], dinv[RPT];
+  double sums[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    x[q] = r[q] = pv[q] = dinv[q] = 0.0;
+    if (i >= nc) continue;
+    if (i > 0) {  // vertex 0 is fixed: its row and column drop out
+      double dg = 0.0;
+      for (int e = krow[i]; e < krow[i + 1]; ++e)
+        if (kcol[e] == i) dg = kval[e];
+      dinv[q] = dg > 0.0 ? 1.0 / dg : 0.0;
+      r[q] = b[i];
+      pv[q] = r[q] * dinv[q];
+      sums[0] += r[q] * r[q];
+      sums[1] += r[q] * pv[q];
+    }
+    p[i] = pv[q];
+  }
+  block_sum<NW, 3>(sums, 2, redA);
+  const double bb = sums[0];
+  double rz = sums[1];
+  bool done = !(bb > 0.0);
+  const double tol2 = rtol * rtol;
+  __syncthreads();
+  int it = 0;
+  bool ok = true;
+  while (!done) {
+    if (it >= maxit) {
+      ok = false;
+      break;
+    }
+    ++it;
+    double ap[RPT];
+    double pq[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = threadIdx.x + q * BLOCK;
+      ap[q] = 0.0;
+      if (i >= nc || i == 0) continue;
+      double s = 0.0;
+      for (int e = krow[i]; e < krow[i + 1]; ++e) s += kval[e] * p[kcol[e]];
+      ap[q] = s;
+      pq[0] += pv[q] * s;
+    }
+    block_sum<NW, 1>(pq, 1, redA);
+    const double alpha = pq[0] != 0.0 ? rz / pq[0] : 0.0;
+    double s2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      x[q] += alpha * pv[q];
+      r[q] -= alpha * ap[q];
+      s2[0] += r[q] * r[q];
+      s2[1] += r[q] * r[q] * dinv[q];
+    }
+    block_sum<NW, 3>(s2, 2, redB);
+    if (s2[0] <= tol2 * bb) break;
+    if (s2[0] != s2[0]) {
+      ok = false;
+      break;
+    }
+    const double beta = rz != 0.0 ? s2[1] / rz : 0.0;
+    rz = s2[1];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = threadIdx.x + q * BLOCK;
+      pv[q] = r[q] * dinv[q] + beta * pv[q];
+      if (i < nc) p[i] = pv[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    if (i < nc) xo[i] = x[q];
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(status + kStCoarseMaxIt, it);
+    if (!ok) atomicAdd(status + kStCoarseNoconv, 1);
+  }
+}
+
+__global__ void k_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,
+                               const double* ent_w, const int* ent_col, const double* colw,
+                               int colw_ld, const double* pval, double* out, int nslot, int ncol,
+                               int nc) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)nslot * ncol) return;
+  const int s = int(t % nslot), j = int(t / nslot);
+  double acc = 0.0;
+  for (int e = slot_ptr[s]; e < slot_ptr[s + 1]; ++e) {
+    double w = ent_w[e] * pval[ent_pidx[e]];
+    if (colw) w *= colw[size_t(j) * colw_ld + ent_col[e]];
+    acc += w;
+  }
+  out[slot_dst[s] + size_t(j) * nc] = acc;
+}
+
+__global__ void k_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
+                       const int* prow, const int* pcol, const double* pval, const double* t, int nc,
+                       double* D) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nr * ns) return;
+  const int i = tid % nr, j = tid / nr;
+  const double* tj = t + size_t(j) * nc;
+  double acc = 0.0;
+  for (int e = rptr[i]; e < rptr[i + 1]; ++e) {
+    const int cell = rcell[e];
+    double uval = 0.0;
+    for (int q = prow[cell]; q < prow[cell + 1]; ++q) uval += pval[q] * tj[pcol[q]];
+    acc += rval[e] * uval;
+  }
+  D[size_t(j) * nr + i] = acc;
+}
+
+__global__ void k_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
+                          int nc, int ns, long long ncell, double* u) {
+  const long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  const int a = prow[cell], b = prow[cell + 1];
+  int col[8];
+  double val[8];
+  const int len = b - a;
+  for (int q = 0; q < 8; ++q) {
+    col[q] = q < len ? pcol[a + q] : 0;
+    val[q] = q < len ? pval[a + q] : 0.0;
+  }
+  for (int j = 0; j < ns; ++j) {
+    const double* tj = t + size_t(j) * nc;
+    double acc = 0.0;
+    for (int q = 0; q < 8; ++q)
+      if (q < len) acc += val[q] * tj[col[q]];
+    u[size_t(j) * ncell + cell] = acc;
+  }
+}
+
+// direct loads at electrode cells: s_c = sum_j t_jc (Rx v_j)(cell) + lambda_jc q_j(cell)
+__global__ void k_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
+                        const double* rw, const int* sptr, const int* sidx, const double* sw,
+                        const int* prow, const int* pcol, const double* t, const double* lam,
+                        const double* v, int nc, int ns, int nr, double* sload) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nelec * 8) return;
+  const int e = tid / 8, c = tid % 8;
+  const int cell = ecell[e];
+  const int a = prow[cell], len = prow[cell + 1] - a;
+  double acc = 0.0;
+  if (c < len) {
+    const int vid = pcol[a + c];
+    for (int j = 0; j < ns; ++j) {
+      double w = 0.0;
+      for (int q = rptr[e]; q < rptr[e + 1]; ++q) w += rw[q] * v[size_t(j) * nr + ridx[q]];
+      acc += t[size_t(j) * nc + vid] * w;
+    }
+    for (int q = sptr[e]; q < sptr[e + 1]; ++q) acc += lam[size_t(sidx[q]) * nc + vid] * sw[q];
+  }
+  sload[e * 8 + c] = acc;
+}
+
+__global__ void k_gfinal(const double* m, const double* W, GridInfo g, long long ncell,
+                         double* grad) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const int x = int(i % g.n[0]);
+  const int y = int((i / g.n[0]) % g.n[1]);
+  const int z = int(i / ((long long)g.n[0] * g.n[1]));
+  const int c[3] = {x, y, z};
+  const double si = exp(m[i]);
+  double acc = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const int st = gstride_of(g, k);
+    const double* Wk = W + k * ncell;
+    if (c[k] + 1 < g.n[k]) acc += dharm(si, exp(m[i + st])) * Wk[i];
+    if (c[k] > 0) acc += dharm(si, exp(m[i - st])) * Wk[i - st];
+  }
+  grad[i] = acc;
+}
+
+__global__ void k_residual(const double* D, const double* dobs, double* v, long long n,
+                           double* phi) {
+  __shared__ double red[16 * 4];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = D[i] - dobs[i];
+    v[i] = r;
+    s += r * r;
+  }
+  double arr[1] = {s};
+  block_sum<16, 1>(arr, 1, red);
+  if (threadIdx.x == 0) phi[0] = 0.5 * arr[0];
+}
+
+template <int BLOCK, int CPT, int NCP>
+size_t local_lds_bytes(const LocalParams& p, bool adj) {
+  const int nw = BLOCK / kWave;
+  size_t d = size_t(p.sig_cap) + size_t(NCP) * p.nu_cap + 2 * nw * 40 + (adj ? 128 : 0);
+  return d * sizeof(double);
+}
+
+template <int BLOCK, int CPT, int NCP>
+hipError_t launch_local_t(const LocalParams& p, bool adj, hipStream_t s) {
+  const size_t lds = local_lds_bytes<BLOCK, CPT, NCP>(p, adj);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (adj) {
+    auto kern = k_local_adj<BLOCK, CPT, NCP>;
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(BLOCK), lds, s, p);
+  } else {
+    auto kern = k_local_fwd<BLOCK, CPT, NCP>;
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(BLOCK), lds, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_local(const LocalParams& p, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  const int nu = p.nu_cap;
+  if (nu <= 64) return launch_local_t<64, 1, 8>(p, adj, s);
+  if (nu <= 128) return launch_local_t<128, 1, 8>(p, adj, s);
+  if (nu <= 256) return launch_local_t<256, 1, 8>(p, adj, s);
+  if (nu <= 384) return launch_local_t<384, 1, 8>(p, adj, s);
+  if (nu <= 512) return launch_local_t<512, 1, 8>(p, adj, s);
+  if (nu <= 1024) return launch_local_t<1024, 1, 4>(p, adj, s);
+  if (nu <= 4096) return launch_local_t<512, 8, 2>(p, adj, s);
+  return hipErrorInvalidConfiguration;
+}
+
+}  // namespace
+
+hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s) {
+  const int threads = 256;
+  long long blocks = (n + threads - 1) / threads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_check_finite, dim3(unsigned(blocks)), dim3(threads), 0, s, m, n, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_fwd, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_adj, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_fwd(const LocalParams& p, int, hipStream_t s) { return launch_local(p, false, s); }
+hipError_t launch_local_adj(const LocalParams& p, int, hipStream_t s) { return launch_local(p, true, s); }
+
+hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_ones, dim3((n + 255) / 256), dim3(256), 0, s, idx, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const double* kent, double* kval,
+                            int nnz, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kassemble, dim3((nnz + 255) / 256), dim3(256), 0, s, kcptr, kcidx, kent, kval, nnz);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_pcg(const int* krow, const int* kcol, const double* kval, const double* rhs,
+                             double* x, int nc, int ncol, double rtol, int maxit, int* status,
+                             double*, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  constexpr int B = 1024;
+  const size_t lds = (size_t(nc) + 2 * (B / kWave) * 4) * sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const int rpt = (nc + B - 1) / B;
+#define MSFV_PCG_CASE(R)                                                                    \
+  if (rpt <= R) {                                                                           \
+    auto kern = k_coarse_pcg<B, R>;                                                         \
+    if (lds > 64 * 1024)                                                                    \
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
+    hipLaunchKernelGGL(kern, dim3(ncol), dim3(B), lds, s, krow, kcol, kval, rhs, x, nc, rtol, maxit, status); \
+    return hipGetLastError();                                                               \
+  }
+  MSFV_PCG_CASE(1)
+  MSFV_PCG_CASE(2)
+  MSFV_PCG_CASE(4)
+  MSFV_PCG_CASE(8)
+  MSFV_PCG_CASE(16)
+#undef MSFV_PCG_CASE
+  return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,
+                               const double* ent_w, const int* ent_col, const double* colw,
+                               int colw_ld, const double* pval, double* out, int nslot, int ncol,
+                               int nc, hipStream_t s) {
+  const long long n = (long long)nslot * ncol;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_slots, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, slot_dst,
+                     slot_ptr, ent_pidx, ent_w, ent_col, colw, colw_ld, pval, out, nslot, ncol, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
+                       const int* prow, const int* pcol, const double* pval, const double* t,
+                       int nc, double* D, hipStream_t s) {
+  const int n = nr * ns;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_data, dim3((n + 255) / 256), dim3(256), 0, s, rptr, rcell, rval, nr, ns, prow,
+                     pcol, pval, t, nc, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
+                          int nc, int ns, long long ncell, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_prolong, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, prow, pcol, pval,
+                     t, nc, ns, ncell, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
+                        const double* rw, const int* sptr, const int* sidx, const double* sw,
+                        const int* prow, const int* pcol, const double* t, const double* lam,
+                        const double* v, int nc, int ns, int nr, double* sload, hipStream_t s) {
+  if (nelec == 0) return hipSuccess;
+  const int n = nelec * 8;
+  hipLaunchKernelGGL(k_sload, dim3((n + 255) / 256), dim3(256), 0, s, nelec, ecell, rptr, ridx, rw,
+                     sptr, sidx, sw, prow, pcol, t, lam, v, nc, ns, nr, sload);
+  return hipGetLastError();
+}
+
+hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long ncell, double* grad,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_gfinal, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, m, W, g, ncell,
+                     grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* D, const double* dobs, double* v, long long n, double* phi,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, s, D, dobs, v, n, phi);
+  return hipGetLastError();
+}
+
+}  // namespace msfv

@@ -1,0 +1,89 @@
+// Launchers of the gfx950 kernels of the MSFV path (implemented in
+// kernels.hip).  All pointers are device pointers; every launcher enqueues
+// on ``stream`` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace msfv {
+
+struct GridInfo {
+  int n[3];
+  int s1, s2;  // cell strides of axes 1 and 2
+};
+
+// status words written by the kernels
+enum StatusSlot {
+  kStNonfinite = 0,
+  kStLocalNoconv = 1,
+  kStLocalMaxIt = 2,
+  kStCoarseNoconv = 3,
+  kStCoarseMaxIt = 4,
+  kStCount = 8
+};
+
+struct LocalParams {
+  const EntDesc* ents = nullptr;  // entities solved by this launch
+  int nent = 0;
+  const EntDesc* recv = nullptr;  // entities receiving adjoint loads (next lower kind)
+  GridInfo g{};
+  const double* m = nullptr;
+  const int* prow = nullptr;
+  const int* pcol = nullptr;
+  double* pval = nullptr;
+  double* kent = nullptr;
+  double rtol = 1e-13;
+  int maxit = 1000;
+  int prescribe = 0;   // forward: Lagrange values instead of a solve
+  int* status = nullptr;
+  int sig_cap = 0;     // LDS doubles reserved for the closure conductivities
+  int nu_cap = 0;      // largest own-cell count in this launch
+  // adjoint
+  const double* t = nullptr;
+  const double* lam = nullptr;
+  int ncoarse = 0;
+  int ns = 0;
+  const double* inbuf = nullptr;   // loads received by these entities
+  double* outbuf = nullptr;        // loads pushed to the receivers
+  const int* eidx = nullptr;       // electrode index per entity electrode slot
+  const int* eloc = nullptr;       // own-cell index of that electrode
+  const double* sload = nullptr;   // direct loads per electrode and corner (8 each)
+  double* W = nullptr;             // 3*N flux weights
+  int solve_adj = 1;               // 0: flux-derivative (G) term only
+  int push = 1;                    // 1: push loads to lower entities
+};
+
+hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
+hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s);
+hipError_t launch_local_fwd(const LocalParams& p, int kind_rmax, hipStream_t s);
+hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s);
+hipError_t launch_local_adj(const LocalParams& p, int kind_rmax, hipStream_t s);
+hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s);
+hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const double* kent, double* kval,
+                            int nnz, hipStream_t s);
+hipError_t launch_coarse_pcg(const int* krow, const int* kcol, const double* kval, const double* rhs,
+                             double* x, int nc, int ncol, double rtol, int maxit, int* status,
+                             double* work, hipStream_t s);
+// out[slot_dst[s] + j*nc] = sum_e w[e] * pval[pidx[e]] * (colw ? colw[j*colw_ld + col[e]] : 1)
+// for slot s and column j < ncol (one thread each).
+hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,
+                               const double* ent_w, const int* ent_col, const double* colw,
+                               int colw_ld, const double* pval, double* out, int nslot,
+                               int ncol, int nc, hipStream_t s);
+hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
+                       const int* prow, const int* pcol, const double* pval, const double* t,
+                       int nc, double* D, hipStream_t s);
+hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
+                          int nc, int ns, long long ncell, double* u, hipStream_t s);
+hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
+                        const double* rw, const int* sptr, const int* sidx, const double* sw,
+                        const int* prow, const int* pcol, const double* t, const double* lam,
+                        const double* v, int nc, int ns, int nr, double* sload, hipStream_t s);
+hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long ncell, double* grad,
+                         hipStream_t s);
+hipError_t launch_residual(const double* D, const double* dobs, double* v, long long n,
+                           double* phi, hipStream_t s);
+
+}  // namespace msfv

@@ -1,0 +1,197 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: S_k, A_k, t, D and u within 1e-10 relative (Frobenius), the
+gradient within 1e-8 relative, as stated for this path; both sides compute
+in FP64.  Grids span several dual blocks, truncated last coarse cells
+(n mod r != 0), empty upper strips (last coarse cell of 1 or 2 cells), both
+boundary modes, 2-D and 3-D.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import Geometry
+from oracle import reduced as R
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((13, 11, 9), (4, 4, 4)),     # truncated last cells on every axis
+    ((16, 12, 10), (4, 3, 5)),    # mixed coarsening
+    ((17, 9, 12), (8, 3, 4)),     # r = 8 with a 1-cell last coarse cell (empty upper strip)
+    ((18, 10, 7), (5, 3, 3)),     # 2-cell last coarse cells
+    ((32, 32), (4, 4)),           # 2-D
+    ((23, 17), (5, 6)),           # 2-D truncated
+]
+MODES = ["reduced", "lagrange"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _problem(n, r, mode, inst, **kw):
+    import paper_1707_07598_amd as msfv
+    prob = msfv.Problem(n, r, mode, **kw)
+    prob.set_sources(inst.sources)
+    prob.set_receivers(inst.receivers)
+    return prob
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _csr(rp, col, val, shape):
+    return sp.csr_matrix((val, col, rp), shape=shape)
+
+
+@pytest.mark.parametrize("n,r", CASES)
+@pytest.mark.parametrize("mode", MODES)
+def test_forward_parity(n, r, mode):
+    torch = _torch()
+    inst = W.small_instance(n, r, seed=11, ns=3, nr=5)
+    g = Geometry(n, r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers, mode)
+    prob = _problem(n, r, mode, inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    D, u = prob.forward(m, want_u=True)
+    # S_k
+    rp, col, val = prob.prolongation()
+    P = _csr(rp, col, val, (g.ncell, g.ncoarse)).toarray()
+    Pref = st.P.toarray()
+    assert _rel(P, Pref) < 1e-10
+    assert np.abs(P - Pref).max() < 1e-10
+    # A_k before the pin
+    (krp, kcol, kval), t = prob.coarse()
+    K = _csr(krp, kcol, kval, (g.ncoarse, g.ncoarse)).toarray()
+    assert _rel(K, st.K) < 1e-10
+    assert _rel(t, st.t.T) < 1e-10
+    assert _rel(D.cpu().numpy(), st.D.T) < 1e-10
+    assert _rel(u.cpu().numpy(), st.u.T) < 1e-10
+    prob.close()
+
+
+@pytest.mark.parametrize("n,r", CASES)
+@pytest.mark.parametrize("mode", MODES)
+def test_gradient_parity(n, r, mode):
+    torch = _torch()
+    inst = W.small_instance(n, r, seed=12, ns=3, nr=5)
+    g = Geometry(n, r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers, mode)
+    rng = np.random.default_rng(3)
+    V = rng.standard_normal(st.D.shape)
+    g_ref = R.jtv(st, V)
+    prob = _problem(n, r, mode, inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    prob.forward(m)
+    gg = prob.jtv(torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert _rel(gg, g_ref) < 1e-8
+    prob.close()
+
+
+def test_misfit_gradient_parity():
+    torch = _torch()
+    n, r = (16, 12, 10), (4, 3, 5)
+    inst = W.small_instance(n, r, seed=13, ns=4, nr=6)
+    g = Geometry(n, r)
+    Dobs = R.forward(g, inst.m_obs, inst.sources, inst.receivers).D
+    phi_ref, g_ref, _ = R.misfit_grad(g, inst.m, inst.sources, inst.receivers, Dobs)
+    prob = _problem(n, r, "reduced", inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    phi, gg = prob.misfit_grad(m, torch.tensor(Dobs.T.copy(), dtype=torch.float64, device="cuda"))
+    assert abs(phi.item() - phi_ref) <= 1e-10 * abs(phi_ref)
+    assert _rel(gg.cpu().numpy(), g_ref) < 1e-8
+    prob.close()
+
+
+def test_small_2d_workload_parity():
+    """The 2-D 32x32, r = 4 workload (one dipole, 16 receivers)."""
+    torch = _torch()
+    inst = W.workload_small_2d()
+    g = Geometry(inst.n, inst.r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers)
+    Dobs = R.forward(g, inst.m_obs, inst.sources, inst.receivers).D
+    g_ref = R.jtv(st, st.D - Dobs)
+    prob = _problem(inst.n, inst.r, "reduced", inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    D = prob.forward(m)
+    assert _rel(D.cpu().numpy(), st.D.T) < 1e-10
+    gg = prob.jtv(torch.tensor((st.D - Dobs).T.copy(), dtype=torch.float64, device="cuda"))
+    assert _rel(gg.cpu().numpy(), g_ref) < 1e-8
+    prob.close()
+
+
+def test_determinism_and_stats():
+    torch = _torch()
+    n, r = (13, 11, 9), (4, 4, 4)
+    inst = W.small_instance(n, r, seed=14, ns=2, nr=3)
+    prob = _problem(n, r, "reduced", inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    v = torch.ones((2, 3), dtype=torch.float64, device="cuda")
+    D1 = prob.forward(m).clone()
+    g1 = prob.jtv(v).clone()
+    D2 = prob.forward(m).clone()
+    g2 = prob.jtv(v).clone()
+    assert torch.equal(D1, D2) and torch.equal(g1, g2)
+    s = prob.stats()
+    assert s.local_noconv == 0 and s.coarse_noconv == 0 and s.nonfinite == 0
+    assert s.local_max_it > 0 and s.coarse_max_it > 0
+    prob.close()
+
+
+def test_error_paths():
+    torch = _torch()
+    import paper_1707_07598_amd as msfv
+    from paper_1707_07598_amd import _lib
+    n, r = (13, 11, 9), (4, 4, 4)
+    inst = W.small_instance(n, r, seed=15, ns=2, nr=3)
+    prob = _problem(n, r, "reduced", inst)
+    v = torch.ones((2, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(msfv.MsfvError) as e:
+        prob.jtv(v)
+    assert e.value.status == _lib.MSFV_ESTATE
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    bad = m.clone()
+    bad[7] = float("nan")
+    with pytest.raises(msfv.MsfvError) as e:
+        prob.forward(bad)
+    assert e.value.status == _lib.MSFV_ENONFINITE
+    prob.forward(m)  # recovers
+    prob.close()
+    capped = _problem(n, r, "reduced", inst, local_maxit=1)
+    with pytest.raises(msfv.MsfvError) as e:
+        capped.forward(m)
+    assert e.value.status == _lib.MSFV_ENOCONV
+    capped.close()
+    with pytest.raises(msfv.MsfvError) as e:
+        msfv.Problem((20, 20, 20), (2, 2, 2))
+    assert e.value.status == _lib.MSFV_EINVAL
+
+
+def test_autograd_function():
+    torch = _torch()
+    import paper_1707_07598_amd as msfv
+    n, r = (13, 11, 9), (4, 4, 4)
+    inst = W.small_instance(n, r, seed=16, ns=2, nr=4)
+    g = Geometry(n, r)
+    Dobs = R.forward(g, inst.m_obs, inst.sources, inst.receivers).D
+    prob = _problem(n, r, "reduced", inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda", requires_grad=True)
+    dobs = torch.tensor(Dobs.T.copy(), dtype=torch.float64, device="cuda")
+    phi = msfv.msfv_misfit(m, prob, dobs)
+    phi.backward()
+    _, g_ref, _ = R.misfit_grad(g, inst.m, inst.sources, inst.receivers, Dobs)
+    assert _rel(m.grad.cpu().numpy(), g_ref) < 1e-8
+    # directional finite difference through the Function
+    e = torch.tensor(np.random.default_rng(5).standard_normal(g.ncell), device="cuda")
+    h = 1e-5
+    with torch.no_grad():
+        fp = msfv.msfv_misfit(m + h * e, prob, dobs).item()
+        fm = msfv.msfv_misfit(m - h * e, prob, dobs).item()
+    fd = (fp - fm) / (2 * h)
+    assert abs(fd - (m.grad * e).sum().item()) <= 1e-5 * abs(fd)
+    prob.close()
