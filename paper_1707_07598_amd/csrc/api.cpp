@@ -49,10 +49,13 @@ struct DevBuf {
     if (count == 0) return hipSuccess;
     return hipMalloc(&ptr, count * sizeof(T));
   }
+  // Blocking upload: the host vector may be a temporary.
   hipError_t upload(const std::vector<T>& h, hipStream_t s) {
     hipError_t e = alloc(h.size());
     if (e != hipSuccess || h.empty()) return e;
-    return hipMemcpyAsync(ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
   }
   size_t bytes() const { return n * sizeof(T); }
 };
@@ -76,8 +79,8 @@ struct msfv_problem {
 
   // plan on the device
   DevBuf<msfv::EntDesc> d_edges, d_faces, d_blocks;
-  DevBuf<int> d_prow, d_pcol, d_krow, d_kcol, d_kcptr, d_kcidx, d_vrows;
-  DevBuf<double> d_pval, d_kval, d_kent, d_inbuf, d_W;
+  DevBuf<int> d_prow, d_pcol, d_krow, d_kcol, d_kcptr, d_kcidx, d_kdslot, d_vrows;
+  DevBuf<double> d_pval, d_kval, d_kdia, d_kent, d_inbuf, d_W;
   DevBuf<double> d_m;  // copy of the m of the last forward
   DevBuf<int> d_status;
 
@@ -97,8 +100,9 @@ struct msfv_problem {
 
   size_t workspace_bytes() const {
     return d_edges.bytes() + d_faces.bytes() + d_blocks.bytes() + d_prow.bytes() + d_pcol.bytes() +
-           d_krow.bytes() + d_kcol.bytes() + d_kcptr.bytes() + d_kcidx.bytes() + d_vrows.bytes() +
-           d_pval.bytes() + d_kval.bytes() + d_kent.bytes() + d_inbuf.bytes() + d_W.bytes() +
+           d_krow.bytes() + d_kcol.bytes() + d_kcptr.bytes() + d_kcidx.bytes() + d_kdslot.bytes() +
+           d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
+           d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
            d_sload.bytes();
   }
@@ -291,6 +295,14 @@ msfv::LocalParams base_params(msfv_problem* p) {
   return lp;
 }
 
+void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
+  lp.nu_cap = nu_cap;
+  lp.lane_cap = c.lane;
+  lp.col_cap = c.col;
+  lp.nc_cap = c.nc;
+  lp.plane_cap = c.plane;
+}
+
 msfv_status ensure_ready(msfv_problem* p) {
   if (p->src.count <= 0) return fail(MSFV_ESTATE, "no sources set");
   if (p->rec.count <= 0) return fail(MSFV_ESTATE, "no receivers set");
@@ -316,7 +328,7 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
   lp.nent = int(P.faces.size());
-  lp.nu_cap = P.max_nu_face;
+  set_caps(lp, P.caps_face, P.max_nu_face);
   lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
   HIP_OK(msfv::launch_local_fwd(lp, 0, s));
 
@@ -324,20 +336,19 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
     lp = base_params(p);
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
-    lp.nu_cap = P.max_nu_block;
+    set_caps(lp, P.caps_block, P.max_nu_block);
     HIP_OK(msfv::launch_local_fwd(lp, 0, s));
   }
-  HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kent.ptr, p->d_kval.ptr,
-                                int(P.kcol.size()), s));
+  HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
+                                p->d_kval.ptr, p->d_kdia.ptr, int(P.kcol.size()), s));
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
   HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
   HIP_OK(msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
                                    p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
                                    p->nsrc_slot, 1, nc, s));
-  HIP_OK(msfv::launch_coarse_pcg(p->d_krow.ptr, p->d_kcol.ptr, p->d_kval.ptr, p->d_b.ptr, p->d_t.ptr,
-                                 nc, ns, p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr,
-                                 nullptr, s));
+  HIP_OK(msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_t.ptr, ns,
+                                 p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr, s));
   HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
                            p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
   if (u_out)
@@ -358,9 +369,8 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   HIP_OK(msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
                                    p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
                                    p->nrec_slot, ns, nc, s));
-  HIP_OK(msfv::launch_coarse_pcg(p->d_krow.ptr, p->d_kcol.ptr, p->d_kval.ptr, p->d_b.ptr,
-                                 p->d_lam.ptr, nc, ns, p->cfg.coarse_rtol, p->cfg.coarse_maxit,
-                                 p->d_status.ptr, nullptr, s));
+  HIP_OK(msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_lam.ptr, ns,
+                                 p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr, s));
   HIP_OK(msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
                             p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
                             p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
@@ -369,7 +379,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp = base_params(p);
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
-    lp.nu_cap = P.max_nu_block;
+    set_caps(lp, P.caps_block, P.max_nu_block);
     lp.recv = p->d_faces.ptr;
     lp.push = lagrange ? 0 : 1;
     lp.solve_adj = 1;
@@ -378,7 +388,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
   lp.nent = int(P.faces.size());
-  lp.nu_cap = P.max_nu_face;
+  set_caps(lp, P.caps_face, P.max_nu_face);
   lp.recv = p->d_edges.ptr;
   lp.push = lagrange ? 0 : 1;
   lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
@@ -460,6 +470,18 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   HIP_OR_CLEAN(p->d_kcol.upload(P.kcol, s));
   HIP_OR_CLEAN(p->d_kcptr.upload(P.kcptr, s));
   HIP_OR_CLEAN(p->d_kcidx.upload(P.kcidx, s));
+  {
+    // diagonal slots with the solver's padded row stride
+    const int ldk = msfv::coarse_ldk(int(P.ncoarse));
+    std::vector<int> slot(P.kdslot.size());
+    for (size_t e = 0; e < slot.size(); ++e) {
+      const int o = int(P.kdslot[e] / P.ncoarse), row = int(P.kdslot[e] % P.ncoarse);
+      slot[e] = o * ldk + row;
+    }
+    HIP_OR_CLEAN(p->d_kdslot.upload(slot, s));
+    HIP_OR_CLEAN(p->d_kdia.alloc(size_t(27) * ldk));
+  }
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_kdia.ptr, 0, p->d_kdia.bytes(), s));
   HIP_OR_CLEAN(p->d_pval.alloc(P.pcol.size()));
   HIP_OR_CLEAN(p->d_kval.alloc(std::max<size_t>(1, P.kcol.size())));
   HIP_OR_CLEAN(p->d_kent.alloc(std::max<int64_t>(1, P.kent_size)));

@@ -40,6 +40,10 @@ struct LocalParams {
   int* status = nullptr;
   int sig_cap = 0;     // LDS doubles reserved for the closure conductivities
   int nu_cap = 0;      // largest own-cell count in this launch
+  int lane_cap = 0;    // largest own-cell plane over the two lane axes
+  int col_cap = 0;     // largest own-cell column along the third axis
+  int nc_cap = 0;      // largest corner count
+  int plane_cap = 0;   // largest zero-padded plane buffer (doubles per wave)
   // adjoint
   const double* t = nullptr;
   const double* lam = nullptr;
@@ -61,11 +65,20 @@ hipError_t launch_local_fwd(const LocalParams& p, int kind_rmax, hipStream_t s);
 hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s);
 hipError_t launch_local_adj(const LocalParams& p, int kind_rmax, hipStream_t s);
 hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s);
-hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const double* kent, double* kval,
-                            int nnz, hipStream_t s);
-hipError_t launch_coarse_pcg(const int* krow, const int* kcol, const double* kval, const double* rhs,
-                             double* x, int nc, int ncol, double rtol, int maxit, int* status,
-                             double* work, hipStream_t s);
+// A_k as CSR (kval) and as 27 diagonals of the coarse grid (kdia[o*ldk + row],
+// o = (dx+1) + 3(dy+1) + 9(dz+1), ldk = coarse_ldk(nc)); dslot maps each CSR
+// nonzero to its slot.
+hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const int* dslot, const double* kent,
+                            double* kval, double* kdia, int nnz, hipStream_t s);
+// Row stride of the diagonal storage used by the coarse solver (rows padded
+// with zeros to a multiple of its workgroup size).
+int coarse_ldk(int nc);
+// Jacobi-PCG on A_k with vertex 0 fixed, one workgroup per column of rhs.
+hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
+                             int ncol, double rtol, int maxit, int* status, hipStream_t s);
+// wave-per-corner local solves (wave_kernels.hip)
+bool wave_path_fits(const LocalParams& p);
+hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);
 // out[slot_dst[s] + j*nc] = sum_e w[e] * pval[pidx[e]] * (colw ? colw[j*colw_ld + col[e]] : 1)
 // for slot s and column j < ncol (one thread each).
 hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,

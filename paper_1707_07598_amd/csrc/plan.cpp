@@ -269,6 +269,48 @@ std::string Plan::build(int dim_, const int n_[3], const int r_[3]) {
     i = j;
   }
   for (int64_t i = 0; i < ncoarse; ++i) krow[i + 1] += krow[i];
+  kdslot.assign(kcol.size(), 0);
+  for (int64_t row = 0; row < ncoarse; ++row)
+    for (int e = krow[row]; e < krow[row + 1]; ++e) {
+      const int col = kcol[e];
+      int o = 0, mul = 1;
+      for (int k = 0; k < 3; ++k) {
+        const int a = int(row / vstride[k]) % ncv[k], b = (col / vstride[k]) % ncv[k];
+        const int d = b - a;
+        if (d < -1 || d > 1) return "coarse operator pattern wider than 27 points";
+        o += (d + 1) * mul;
+        mul *= 3;
+      }
+      kdslot[e] = int(o * ncoarse + row);
+    }
+
+  // lane / column caps of the wave-per-corner local solves
+  auto caps_of = [&](const std::vector<EntDesc>& list, Caps* c) {
+    for (const auto& e : list) {
+      int axa, axb, axc;
+      if (e.open_mask == 7) {
+        axa = 0, axb = 1, axc = 2;
+      } else {
+        int o[3], no = 0, pl = 0;
+        for (int k = 0; k < 3; ++k) {
+          if (e.open_mask >> k & 1)
+            o[no++] = k;
+          else
+            pl = k;
+        }
+        axa = o[0], axb = o[1], axc = pl;
+      }
+      const int ua = e.uext[axa], ub = e.uext[axb], L = e.uext[axc];
+      c->lane = std::max(c->lane, ua * ub);
+      c->col = std::max(c->col, L);
+      c->nc = std::max(c->nc, e.nc);
+      c->plane = std::max(c->plane, (ua + 2) * (ub + 2) * L);
+    }
+  };
+  caps_face = Caps();
+  caps_block = Caps();
+  caps_of(faces, &caps_face);
+  caps_of(blocks, &caps_block);
 
   // ---- structure of S_k -----------------------------------------------------
   prow.assign(ncell + 1, 0);

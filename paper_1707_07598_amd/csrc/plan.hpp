@@ -71,11 +71,17 @@ struct Plan {
 
   std::vector<int> prow, pcol;     // S_k CSR structure
   std::vector<int> krow, kcol;     // A_k CSR structure
+  std::vector<int> kdslot;         // per A_k nonzero: slot o*ncoarse + row of its diagonal o
   std::vector<int> kcptr, kcidx;   // per A_k nonzero: energy-block entries summed into it
   int64_t kent_size = 0;           // doubles in the energy-block buffer
   int64_t inbuf_size = 0;          // doubles in the adjoint-load buffer
   int max_closure = 0;             // largest closure box (cells)
   int max_nu_face = 0, max_nu_block = 0, max_nu_edge = 0;
+  // geometry caps of a launch over faces or blocks (lane plane, column, corners,
+  // zero-padded plane buffer); see the wave-per-corner kernels
+  struct Caps {
+    int lane = 0, col = 0, nc = 0, plane = 0;
+  } caps_face, caps_block;
 
   // Build; returns an empty string on success or an error message.
   std::string build(int dim, const int n[3], const int r[3]);

@@ -1,0 +1,638 @@
+// Wave-per-corner local solves for faces and dual blocks whose own cells fit
+// a 64-lane plane (coarsening r <= 8).
+//
+// A workgroup handles one entity E (a face or a dual block).  After a shared
+// setup (closure conductivities, two-point transmissibilities and the Jacobi
+// scaling d^{-1/2}), wavefront c works on corner c of E alone: the corners
+// are independent right-hand sides of the same local matrix, so the
+// conjugate-gradient iteration needs no workgroup barrier.  Lane l owns the
+// column (ia, ib) of the entity's own-cell box over its two lane axes and
+// keeps the column's cells along the third axis in registers; neighbours
+// along the lane axes are exchanged through a zero-padded plane buffer in LDS
+// (Dirichlet and outside neighbours read 0), neighbours along the column come
+// from registers.  CG runs on the symmetrically scaled operator
+// D^{-1/2} A D^{-1/2} (Jacobi-PCG on A in exact arithmetic) with two
+// wavefront reductions per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace msfv {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double p_lookup(const int* __restrict__ prow, const int* __restrict__ pcol,
+                                           const double* __restrict__ pval, int gid, int vid) {
+  const int a = prow[gid], b = prow[gid + 1];
+  double v = 0.0;
+  for (int e = a; e < b; ++e)
+    if (pcol[e] == vid) v = pval[e];
+  return v;
+}
+
+__device__ __forceinline__ int sel3(int k, int a0, int a1, int a2) {
+  return k == 0 ? a0 : (k == 1 ? a1 : a2);
+}
+
+// Lane / column geometry of an entity: lane axes a, b and column axis c, with
+// strides of each in own-cell index space (u), global cell space (g) and
+// closure space (s).
+struct WGeo {
+  int axa, axb, axc;
+  int Ua, Ub, L;
+  int ua, ub, uc;  // own-index strides
+  int ga, gb, gc;  // global strides
+  int sa, sb, sc;  // closure strides
+  int pa, plane;   // padded row length and padded plane size
+  int g0, s0;      // global id and closure index of the own-box origin
+};
+
+__device__ __forceinline__ WGeo wave_geo(const EntDesc& E, const GridInfo& g) {
+  WGeo w;
+  if (E.open_mask == 7) {
+    w.axa = 0;
+    w.axb = 1;
+    w.axc = 2;
+  } else {
+    // the two open axes are the lane axes; the plane axis is the column
+    w.axc = (E.open_mask & 1) == 0 ? 0 : ((E.open_mask & 2) == 0 ? 1 : 2);
+    w.axa = w.axc == 0 ? 1 : 0;
+    w.axb = w.axc == 2 ? 1 : 2;
+  }
+  const int us1 = E.uext[0], us2 = E.uext[0] * E.uext[1];
+  const int cs1 = E.cext[0], cs2 = E.cext[0] * E.cext[1];
+  w.Ua = sel3(w.axa, E.uext[0], E.uext[1], E.uext[2]);
+  w.Ub = sel3(w.axb, E.uext[0], E.uext[1], E.uext[2]);
+  w.L = sel3(w.axc, E.uext[0], E.uext[1], E.uext[2]);
+  w.ua = sel3(w.axa, 1, us1, us2);
+  w.ub = sel3(w.axb, 1, us1, us2);
+  w.uc = sel3(w.axc, 1, us1, us2);
+  w.ga = sel3(w.axa, 1, g.s1, g.s2);
+  w.gb = sel3(w.axb, 1, g.s1, g.s2);
+  w.gc = sel3(w.axc, 1, g.s1, g.s2);
+  w.sa = sel3(w.axa, 1, cs1, cs2);
+  w.sb = sel3(w.axb, 1, cs1, cs2);
+  w.sc = sel3(w.axc, 1, cs1, cs2);
+  w.pa = w.Ua + 2;
+  w.plane = (w.Ua + 2) * (w.Ub + 2);
+  w.g0 = E.ulo[0] + g.s1 * E.ulo[1] + g.s2 * E.ulo[2];
+  w.s0 = (E.ulo[0] - E.clo[0]) + cs1 * (E.ulo[1] - E.clo[1]) + cs2 * (E.ulo[2] - E.clo[2]);
+  return w;
+}
+
+// Neighbour classes of the cell at lane position (ia, ib) and column index k:
+// bit d = 2*axis + plus of fm: the reduced operator has that flux; of um:
+// the neighbour is an own cell.
+__device__ __forceinline__ void cell_masks(const EntDesc& E, const WGeo& w, int ia, int ib, int k,
+                                           int* fm, int* um) {
+  int f = 0, u = 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (!((E.open_mask >> ax) & 1)) continue;
+    const int own = ax == w.axa ? ia : (ax == w.axb ? ib : k);
+    const int ext = sel3(ax, E.uext[0], E.uext[1], E.uext[2]);
+    const int off = sel3(ax, E.ulo[0] - E.clo[0], E.ulo[1] - E.clo[1], E.ulo[2] - E.clo[2]);
+    const int cext = sel3(ax, E.cext[0], E.cext[1], E.cext[2]);
+    const int cl = own + off;
+    if (cl - 1 >= 0) f |= 1 << (2 * ax);
+    if (cl + 1 < cext) f |= 1 << (2 * ax + 1);
+    if (own - 1 >= 0) u |= 1 << (2 * ax);
+    if (own + 1 < ext) u |= 1 << (2 * ax + 1);
+  }
+  *fm = f;
+  *um = u & f;
+}
+
+__device__ __forceinline__ int axis_stride(const WGeo& w, int ax, int which) {
+  // which: 0 own-index, 1 global, 2 closure
+  if (ax == w.axa) return which == 0 ? w.ua : (which == 1 ? w.ga : w.sa);
+  if (ax == w.axb) return which == 0 ? w.ub : (which == 1 ? w.gb : w.sb);
+  return which == 0 ? w.uc : (which == 1 ? w.gc : w.sc);
+}
+
+// sigma on the closure, sqrt of the operator diagonal, scaled transmissibilities
+template <int BLOCK>
+__device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* __restrict__ m,
+                             double* sig, double* dsq, double* tt, const WGeo& w) {
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  for (int i = threadIdx.x; i < ncl; i += BLOCK) {
+    const int lx = i % E.cext[0];
+    const int t = i / E.cext[0];
+    const int ly = t % E.cext[1];
+    const int lz = t / E.cext[1];
+    sig[i] = exp(m[(E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz)]);
+  }
+  __syncthreads();
+  const int ncol = w.Ua * w.Ub;
+  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
+    const int col = i % ncol, k = i / ncol;
+    const int ia = col % w.Ua, ib = col / w.Ua;
+    int fm, um;
+    cell_masks(E, w, ia, ib, k, &fm, &um);
+    const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+    double d = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < 6; ++dd)
+      if ((fm >> dd) & 1) {
+        const int st = axis_stride(w, dd >> 1, 2);
+        d += harm(sig[ci], sig[ci + ((dd & 1) ? st : -st)]);
+      }
+    dsq[ia * w.ua + ib * w.ub + k * w.uc] = sqrt(d);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
+    const int col = i % ncol, k = i / ncol;
+    const int ia = col % w.Ua, ib = col / w.Ua;
+    int fm, um;
+    cell_masks(E, w, ia, ib, k, &fm, &um);
+    const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+    const int u = ia * w.ua + ib * w.ub + k * w.uc;
+#pragma unroll
+    for (int dd = 0; dd < 6; ++dd) {
+      double v = 0.0;
+      if ((um >> dd) & 1) {
+        const int sgn = (dd & 1) ? 1 : -1;
+        v = harm(sig[ci], sig[ci + sgn * axis_stride(w, dd >> 1, 2)]) /
+            (dsq[u] * dsq[u + sgn * axis_stride(w, dd >> 1, 0)]);
+      }
+      tt[dd * E.nu + u] = v;
+    }
+  }
+}
+
+// One lane's column of scaled transmissibilities along the lane axes and the column.
+template <int LMAX>
+struct Column {
+  double tz[LMAX], tam[LMAX], tap[LMAX], tbm[LMAX], tbp[LMAX];
+};
+
+template <int LMAX>
+__device__ __forceinline__ void load_column(const EntDesc& E, const WGeo& w, bool valid, int ia, int ib,
+                                            const double* tt, Column<LMAX>& C) {
+#pragma unroll
+  for (int k = 0; k < LMAX; ++k) {
+    C.tz[k] = C.tam[k] = C.tap[k] = C.tbm[k] = C.tbp[k] = 0.0;
+    if (!valid || k >= w.L) continue;
+    const int u = ia * w.ua + ib * w.ub + k * w.uc;
+    C.tam[k] = tt[(2 * w.axa) * E.nu + u];
+    C.tap[k] = tt[(2 * w.axa + 1) * E.nu + u];
+    C.tbm[k] = tt[(2 * w.axb) * E.nu + u];
+    C.tbp[k] = tt[(2 * w.axb + 1) * E.nu + u];
+    C.tz[k] = tt[(2 * w.axc + 1) * E.nu + u];
+  }
+}
+
+// Conjugate gradients on the scaled operator for one corner, run by one
+// wavefront.  y holds the scaled right-hand side on entry and the scaled
+// solution on exit.  pbuf: this wave's padded plane buffer.
+template <int LMAX>
+__device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
+                       double (&y)[LMAX], double* pbuf, double tol2, int maxit, bool* ok) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int i = lane; i < w.plane * w.L; i += kWave) pbuf[i] = 0.0;
+  wave_sync_lds();
+  const int pidx = (ib + 1) * w.pa + (ia + 1);
+  double r[LMAX], p[LMAX];
+  double rr = 0.0;
+#pragma unroll
+  for (int k = 0; k < LMAX; ++k) {
+    r[k] = y[k];
+    p[k] = y[k];
+    y[k] = 0.0;
+    rr += r[k] * r[k];
+  }
+  rr = wsum(rr);
+  const double bb = rr;
+  int it = 0;
+  *ok = true;
+  if (!(bb > 0.0)) return 0;
+  while (true) {
+    if (it >= maxit) {
+      *ok = false;
+      break;
+    }
+    ++it;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k)
+        if (k < w.L) pbuf[k * w.plane + pidx] = p[k];
+    }
+    wave_sync_lds();
+    double q[LMAX];
+    double pq = 0.0;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      double s = p[k];
+      if (k > 0) s -= C.tz[k - 1] * p[k - 1];
+      if (k + 1 < LMAX) s -= C.tz[k] * p[k + 1];
+      if (valid && k < w.L) {
+        const double* pl = pbuf + k * w.plane + pidx;
+        s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
+      }
+      q[k] = s;
+      pq += p[k] * s;
+    }
+    pq = wsum(pq);
+    const double alpha = pq != 0.0 ? rr / pq : 0.0;
+    double rn = 0.0;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      y[k] += alpha * p[k];
+      r[k] -= alpha * q[k];
+      rn += r[k] * r[k];
+    }
+    rn = wsum(rn);
+    if (rn <= tol2 * bb) break;
+    if (rn != rn) {
+      *ok = false;
+      break;
+    }
+    const double beta = rn / rr;
+    rr = rn;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) p[k] = r[k] + beta * p[k];
+    wave_sync_lds();  // all lanes finished reading the previous directions
+  }
+  return it;
+}
+
+__device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[3], int ci) {
+  double v = 1.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (!((E.bounded_mask >> k) & 1)) continue;
+    const double lo = E.clo[k], hi = E.clo[k] + E.cext[k] - 1;
+    const double x = gc[k];
+    const bool upper = (E.cbits >> (3 * ci + k)) & 1;
+    v *= upper ? (x - lo) / (hi - lo) : (hi - x) / (hi - lo);
+  }
+  return v;
+}
+
+struct WaveLds {
+  double* sig;
+  double* dsq;
+  double* tt;    // 6 * nu (aliases pbuf)
+  double* pbuf;  // NWAVE * plane_cap
+  double* Mm;
+  double* Sm;
+};
+
+template <int NWAVE>
+__device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
+  WaveLds L;
+  L.sig = lds;
+  L.dsq = L.sig + a.sig_cap;
+  L.Mm = L.dsq + a.nu_cap;
+  L.Sm = L.Mm + 64;
+  double* uni = L.Sm + 64;
+  L.tt = uni;
+  L.pbuf = uni;
+  return L;
+}
+
+// receiver-local own index of the neighbour across direction dd of cell (gcx, gcy, gcz)
+__device__ __forceinline__ int receiver_index(const EntDesc& R, int gx, int gy, int gz) {
+  return (gx - R.ulo[0]) + R.uext[0] * ((gy - R.ulo[1]) + R.uext[1] * (gz - R.ulo[2]));
+}
+
+__device__ __forceinline__ int corner_in(const EntDesc& R, int vid) {
+  int ct = -1;
+  for (int q = 0; q < R.nc; ++q)
+    if (R.vid[q] == vid) ct = q;
+  return ct;
+}
+
+// ---------------------------------------------------------------------------
+template <int NWAVE, int LMAX>
+__global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
+  extern __shared__ double lds[];
+  constexpr int BLOCK = NWAVE * 64;
+  const EntDesc& E = a.ents[blockIdx.x];
+  const WaveLds S = carve<NWAVE>(a, lds);
+  const int nc = E.nc;
+  const WGeo w = wave_geo(E, a.g);
+  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  __syncthreads();
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int ia = lane % w.Ua, ib = lane / w.Ua;
+  const bool valid = lane < w.Ua * w.Ub;
+  const bool active = wid < nc;
+  Column<LMAX> C;
+  if (active && !a.prescribe) load_column<LMAX>(E, w, valid, ia, ib, S.tt, C);
+  __syncthreads();  // tt is dead from here on; pbuf aliases it
+  double* pbuf = S.pbuf + wid * a.plane_cap;
+  if (active) {
+    const int vid = E.vid[wid];
+    double y[LMAX];
+    if (!a.prescribe) {
+      // scaled right-hand side: sum over Dirichlet neighbours T phi_c(n)
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        y[k] = 0.0;
+        if (!valid || k >= w.L) continue;
+        int fm, um;
+        cell_masks(E, w, ia, ib, k, &fm, &um);
+        const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+        const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+        double b = 0.0;
+        for (int dd = 0; dd < 6; ++dd) {
+          if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
+          const int sgn = (dd & 1) ? 1 : -1;
+          const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
+          b += T * p_lookup(a.prow, a.pcol, a.pval, gid + sgn * axis_stride(w, dd >> 1, 1), vid);
+        }
+        y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
+      }
+      bool ok = true;
+      const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+      if (lane == 0) {
+        atomicMax(a.status + kStLocalMaxIt, it);
+        if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+      }
+      wave_sync_lds();
+    }
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      if (!valid || k >= w.L) continue;
+      const int u = ia * w.ua + ib * w.ub + k * w.uc;
+      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      double x;
+      if (a.prescribe) {
+        int gcv[3];
+        gcv[0] = gid % a.g.n[0];
+        gcv[1] = (gid / a.g.n[0]) % a.g.n[1];
+        gcv[2] = gid / (a.g.n[0] * a.g.n[1]);
+        x = lagrange_value(E, gcv, wid);
+      } else {
+        x = y[k] / S.dsq[u];
+      }
+      a.pval[a.prow[gid] + wid] = x;
+      pbuf[u] = x;
+    }
+  }
+  __syncthreads();
+  // energy row K_E[c][:] = sum over the touched fluxes T dphi_c dphi^T
+  if (active) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int k = 0; k < w.L; ++k) {
+      if (!valid) break;
+      int fm, um;
+      cell_masks(E, w, ia, ib, k, &fm, &um);
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      const int u = ia * w.ua + ib * w.ub + k * w.uc;
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!((fm >> dd) & 1)) continue;
+        const bool own = (um >> dd) & 1;
+        if (!(dd & 1) && own) continue;  // counted from the lower own cell
+        const int sgn = (dd & 1) ? 1 : -1;
+        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
+        const int un = u + sgn * axis_stride(w, dd >> 1, 0);
+        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
+        double dp[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          dp[q] = 0.0;
+          if (q >= nc) continue;
+          const double pu = S.pbuf[q * a.plane_cap + u];
+          const double pn = own ? S.pbuf[q * a.plane_cap + un] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]);
+          dp[q] = pu - pn;
+        }
+        double dpc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dpc = (q == wid) ? dp[q] : dpc;
+        const double tc = T * dpc;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += tc * dp[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = wsum(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nc) a.kent[E.kbase + wid * nc + q] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int NWAVE, int LMAX>
+__global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
+  extern __shared__ double lds[];
+  constexpr int BLOCK = NWAVE * 64;
+  const EntDesc& E = a.ents[blockIdx.x];
+  const WaveLds S = carve<NWAVE>(a, lds);
+  const int nc = E.nc;
+  const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
+  const WGeo w = wave_geo(E, a.g);
+  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  if (threadIdx.x < nc * nc) {
+    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+    double s = 0.0;
+    for (int j = 0; j < a.ns; ++j)
+      s += a.t[size_t(j) * a.ncoarse + E.vid[q]] * a.lam[size_t(j) * a.ncoarse + E.vid[q2]];
+    S.Mm[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nc * nc) {
+    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+    S.Sm[threadIdx.x] = S.Mm[q * nc + q2] + S.Mm[q2 * nc + q];
+  }
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int ia = lane % w.Ua, ib = lane / w.Ua;
+  const bool valid = lane < w.Ua * w.Ub;
+  const bool active = wid < nc && a.solve_adj;
+  Column<LMAX> C;
+  if (active) load_column<LMAX>(E, w, valid, ia, ib, S.tt, C);
+  __syncthreads();  // tt is dead; pbuf aliases it
+  double* pbuf = S.pbuf + wid * a.plane_cap;
+  if (active) {
+    const int c = wid;
+    double y[LMAX];
+    // load z_c = pushes + electrode loads - (A^E y_c) on own cells, scaled;
+    // the y-part of the pushes to Dirichlet neighbours is written here
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      y[k] = 0.0;
+      if (!valid || k >= w.L) continue;
+      int fm, um;
+      cell_masks(E, w, ia, ib, k, &fm, &um);
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      const int u = ia * w.ua + ib * w.ub + k * w.uc;
+      double z = 0.0;
+      for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
+      for (int e = E.eptr0; e < E.eptr1; ++e)
+        if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
+      const int base = a.prow[gid];
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!((fm >> dd) & 1)) continue;
+        const bool own = (um >> dd) & 1;
+        const int sgn = (dd & 1) ? 1 : -1;
+        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
+        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
+        const int nbase = a.prow[gn];
+        double dy = 0.0;
+        for (int q = 0; q < nc; ++q) {
+          const double pn = own ? a.pval[nbase + q] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]);
+          dy += S.Sm[q * nc + c] * (a.pval[base + q] - pn);
+        }
+        z -= T * dy;
+        if (!own && a.push) {
+          const int te = E.side_ent[dd];
+          if (te >= 0) {
+            const EntDesc& R = a.recv[te];
+            const int ct = corner_in(R, E.vid[c]);
+            if (ct >= 0) {
+              const int gx = gn % a.g.n[0], gy = (gn / a.g.n[0]) % a.g.n[1], gz = gn / (a.g.n[0] * a.g.n[1]);
+              a.outbuf[R.inbase + (E.side_slot[dd] * R.nc + ct) * R.nu + receiver_index(R, gx, gy, gz)] = T * dy;
+            }
+          }
+        }
+      }
+      y[k] = z / S.dsq[u];
+    }
+    bool ok = true;
+    const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+    if (lane == 0) {
+      atomicMax(a.status + kStLocalMaxIt, it);
+      if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+    }
+    wave_sync_lds();
+    // mu_c into this wave's buffer; mu-part of the pushes
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      if (!valid || k >= w.L) continue;
+      const int u = ia * w.ua + ib * w.ub + k * w.uc;
+      const double mu = y[k] / S.dsq[u];
+      pbuf[u] = mu;
+      if (!a.push) continue;
+      int fm, um;
+      cell_masks(E, w, ia, ib, k, &fm, &um);
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
+        const int te = E.side_ent[dd];
+        if (te < 0) continue;
+        const EntDesc& R = a.recv[te];
+        const int ct = corner_in(R, E.vid[c]);
+        if (ct < 0) continue;
+        const int sgn = (dd & 1) ? 1 : -1;
+        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
+        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
+        const int gx = gn % a.g.n[0], gy = (gn / a.g.n[0]) % a.g.n[1], gz = gn / (a.g.n[0] * a.g.n[1]);
+        a.outbuf[R.inbase + (E.side_slot[dd] * R.nc + ct) * R.nu + receiver_index(R, gx, gy, gz)] += T * mu;
+      }
+    }
+  }
+  __syncthreads();
+  // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for owned fluxes
+  const int ncol = w.Ua * w.Ub;
+  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
+    const int col = i % ncol, k = i / ncol;
+    const int ja = col % w.Ua, jb = col / w.Ua;
+    int fm, um;
+    cell_masks(E, w, ja, jb, k, &fm, &um);
+    const int gid = w.g0 + ja * w.ga + jb * w.gb + k * w.gc;
+    const int u = ja * w.ua + jb * w.ub + k * w.uc;
+    const int base = a.prow[gid];
+    for (int dd = 0; dd < 6; ++dd) {
+      if (!((fm >> dd) & 1)) continue;
+      const bool own = (um >> dd) & 1;
+      if (!(dd & 1) && own) continue;
+      const int sgn = (dd & 1) ? 1 : -1;
+      const int un = u + sgn * axis_stride(w, dd >> 1, 0);
+      const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
+      const int nbase = a.prow[gn];
+      double dp[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        dp[q] = q < nc ? a.pval[base + q] - (own ? a.pval[nbase + q] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]))
+                       : 0.0;
+      double wv = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q >= nc) continue;
+        double mq = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < 8; ++q2)
+          if (q2 < nc) mq += S.Mm[q * nc + q2] * dp[q2];
+        wv -= dp[q] * mq;
+        if (a.solve_adj) {
+          const double mun = own ? S.pbuf[q * a.plane_cap + un] : 0.0;
+          wv -= (S.pbuf[q * a.plane_cap + u] - mun) * dp[q];
+        }
+      }
+      const int ax = dd >> 1;
+      a.W[ax * N + ((dd & 1) ? gid : gn)] = wv;
+    }
+  }
+}
+
+template <int NWAVE>
+size_t wave_lds_bytes(const LocalParams& p) {
+  const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
+  return (size_t(p.sig_cap) + p.nu_cap + 128 + uni) * sizeof(double);
+}
+
+template <int NWAVE, int LMAX>
+hipError_t launch_wave_t(const LocalParams& p, bool adj, hipStream_t s) {
+  const size_t lds = wave_lds_bytes<NWAVE>(p);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (adj) {
+    auto kern = k_wave_adj<NWAVE, LMAX>;
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
+  } else {
+    auto kern = k_wave_fwd<NWAVE, LMAX>;
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool wave_path_fits(const LocalParams& p) {
+  return p.lane_cap <= 64 && p.col_cap <= 7 && p.nc_cap <= 8;
+}
+
+hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!wave_path_fits(p)) return hipErrorInvalidConfiguration;
+  if (p.nc_cap <= 4) {
+    if (p.col_cap <= 1) return launch_wave_t<4, 1>(p, adj, s);
+    if (p.col_cap <= 3) return launch_wave_t<4, 3>(p, adj, s);
+    return launch_wave_t<4, 7>(p, adj, s);
+  }
+  if (p.col_cap <= 1) return launch_wave_t<8, 1>(p, adj, s);
+  if (p.col_cap <= 3) return launch_wave_t<8, 3>(p, adj, s);
+  return launch_wave_t<8, 7>(p, adj, s);
+}
+
+}  // namespace msfv
