@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""MSFV forward + J^T v throughput on one MI355X.
+
+Workload: 3-D 128^3 cell-centred diffusion grid, coarsening 8 (16^3 coarse
+vertices), log-conductivity = Gaussian random field (std 1.5, correlation
+length 16 cells, contrast clipped at 1e3), 32 surface dipole sources, 1024
+surface pole receivers, reduced-boundary multiscale basis, FP64.
+
+One step = one misfit-gradient evaluation: rebuild of the basis S_k(m), the
+Galerkin coarse operator, the coarse solves for all 32 sources, the data,
+the residual against observed data, and J_k^T of that residual through the
+change of basis (one "solve" in solves/s).  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MSFV forward+J^T v solves/s at 128^3 r=8; % HBM roofline; serve p50/p99 latency"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+LDS_PEAK_TBS = 78.6          # 256 CUs x 128 B/clk x 2.4 GHz
+# algorithmic flops of one conjugate-gradient cell-iteration of the local
+# solves (6 neighbour FMAs of the scaled operator, 5 vector FMAs) and of one
+# coarse row-iteration (27 FMAs of the stencil, 5 vector FMAs)
+FLOPS_PER_LOCAL_CELL_IT = 22.0
+FLOPS_PER_COARSE_ROW_IT = 64.0
+LDS_BYTES_PER_LOCAL_CELL_IT = 40.0  # 4 neighbour reads + 1 write of the search direction
+
+STAGE_WORK = {
+    "block_fwd": ("block_fwd_cell_its", FLOPS_PER_LOCAL_CELL_IT),
+    "block_adj": ("block_adj_cell_its", FLOPS_PER_LOCAL_CELL_IT),
+    "face_fwd": ("face_fwd_cell_its", FLOPS_PER_LOCAL_CELL_IT),
+    "face_adj": ("face_adj_cell_its", FLOPS_PER_LOCAL_CELL_IT),
+    "coarse_fwd": ("coarse_fwd_row_its", FLOPS_PER_COARSE_ROW_IT),
+    "coarse_adj": ("coarse_adj_row_its", FLOPS_PER_COARSE_ROW_IT),
+}
+
+
+def cpu_baseline(inst) -> dict:
+    """The CPU oracle timed on a bounded sample of the same workload: the
+    bottom 128 x 128 x 64 half of the 128^3 field (every electrode and
+    receiver lies on the surface k = 0, so their cell ids are unchanged),
+    forward + J^T v, scaled by the cell ratio to solves/s of the full grid."""
+    import numpy as np
+
+    from oracle import Geometry
+    from oracle import reduced as R
+
+    nz = 64
+    n = (inst.n[0], inst.n[1], nz)
+    m = inst.m.reshape(inst.n[::-1])[:nz].reshape(-1).copy()
+    g = Geometry(n, inst.r)
+    t0 = time.perf_counter()
+    st = R.forward(g, m, inst.sources, inst.receivers)
+    v = np.ones_like(st.D)
+    R.jtv(st, v)
+    dt = time.perf_counter() - t0
+    scale = inst.n[2] / nz
+    cores = len(os.sched_getaffinity(0))
+    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle forward + J^T v on the 128x128x{nz} surface slab of the 128^3 field "
+                      f"(r=8, 32 dipoles, 1024 receivers; {dt:.1f} s), scaled x{scale:g} by cell count; "
+                      "one process, NumPy/SciPy with BLAS threads = cores",
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-stage events")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1707_07598_amd as msfv
+    import workloads as W
+
+    inst = W.workload_128()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    prob = msfv.Problem(inst.n, inst.r, "reduced")
+    prob.set_sources(inst.sources)
+    prob.set_receivers(inst.receivers)
+    m = torch.tensor(inst.m, dtype=torch.float64, device=dev)
+    m_obs = torch.tensor(inst.m_obs, dtype=torch.float64, device=dev)
+    d_obs = prob.forward(m_obs).clone()
+
+    for _ in range(args.warmup):
+        prob.misfit_grad(m, d_obs, sync=False)
+    prob.sync()
+    if not args.no_profile:
+        prob.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phi, g = prob.misfit_grad(m, d_obs, sync=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.sync()  # raises on a non-converged or non-finite step
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
+    stats = prob.stats()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3d-128^3-r8-32dipoles-1024rx-forward+JTv",
+                   "n": list(inst.n), "r": list(inst.r), "sources": int(prob.ns),
+                   "receivers": int(prob.nr), "bc_mode": "reduced",
+                   "local_rtol": 1e-13, "coarse_rtol": 1e-13},
+        "source_solves_per_s": value * prob.ns,
+        "local_cg_max_it": stats.local_max_it,
+        "coarse_cg_max_it": stats.coarse_max_it,
+    }
+
+    if not args.no_profile:
+        prof = prob.profile_read()
+        stages = prof["stages"]
+        work = prof["work"]
+        out["stages_ms_per_step"] = {k: v["ms"] / args.steps for k, v in
+                                     sorted(stages.items(), key=lambda kv: -kv[1]["ms"])}
+        dom = max((k for k in stages if k in STAGE_WORK), key=lambda k: stages[k]["ms"])
+        launches = stages[dom]["count"]
+        avg_s = stages[dom]["ms"] / launches / 1e3
+        key, flops_per_unit = STAGE_WORK[dom]
+        units_per_launch = work[key] / launches
+        achieved = flops_per_unit * units_per_launch / avg_s / 1e12
+        out["roofline"] = {
+            "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": dom, "avg_launch_ms": avg_s * 1e3, "units_per_launch": units_per_launch,
+            "unit_kind": key, "flops_per_unit": flops_per_unit,
+        }
+        if dom.startswith(("block", "face")):
+            lds = LDS_BYTES_PER_LOCAL_CELL_IT * units_per_launch / avg_s / 1e12
+            out["roofline"]["lds_tb_per_s"] = lds
+            out["roofline"]["lds_frac"] = lds / LDS_PEAK_TBS
+        # HBM view of the streaming part: algorithmic bytes of the whole step
+        sz = prob.sizes()
+        hbm_bytes = 8 * sz.ncell * 3 + 12 * sz.nnz_p * 2
+        out["hbm_algorithmic_bytes_per_step"] = hbm_bytes
+        out["hbm_frac_of_step"] = hbm_bytes / (ms_per_step / 1e3) / 8e12
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst)
+    prob.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

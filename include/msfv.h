@@ -107,8 +107,9 @@ typedef struct {
 
 /* Create a problem for one grid; builds the plan (entity tables, CSR
  * structure of S_k and A_k) and allocates its device state.  hip_stream is a
- * hipStream_t (NULL = default stream).  Unsupported geometry (r outside
- * [3, 16], n < 2r on some axis) returns MSFV_EINVAL. */
+ * hipStream_t (NULL = default stream).  Unsupported geometry returns
+ * MSFV_EINVAL: r outside [3, 16], n < 2 on an axis, or more than 16384
+ * coarse vertices. */
 msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem** out);
 
 /* Release all device and host state.  NULL is ignored. */
@@ -148,6 +149,32 @@ msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out);
 msfv_status msfv_get_prolongation(msfv_problem* p, int* row_ptr, int* col, double* val);
 msfv_status msfv_get_coarse(msfv_problem* p, int* row_ptr, int* col, double* val, double* t_out);
 msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out);
+
+/* Stage profiling.  When enabled, every stage launched by msfv_forward,
+ * msfv_jtv and msfv_misfit_grad is bracketed by HIP events on the problem's
+ * stream; msfv_profile_read() synchronises, returns the summed event time
+ * and launch count per stage since the previous read, plus work counters,
+ * and resets them.  work[0..3]: local CG cell-iterations (sum over local
+ * solves of iterations x own cells) of dual blocks forward / adjoint and of
+ * faces (3-D) or 2-D blocks forward / adjoint; work[4..5]: coarse CG
+ * row-iterations (iterations x coarse rows) forward / adjoint. */
+enum {
+  MSFV_STAGE_COPY_M = 0, MSFV_STAGE_CHECK, MSFV_STAGE_EDGE_FWD, MSFV_STAGE_FACE_FWD,
+  MSFV_STAGE_BLOCK_FWD, MSFV_STAGE_KASSEMBLE, MSFV_STAGE_COARSE_RHS, MSFV_STAGE_COARSE_FWD,
+  MSFV_STAGE_DATA, MSFV_STAGE_PROLONG, MSFV_STAGE_ADJ_RHS, MSFV_STAGE_COARSE_ADJ,
+  MSFV_STAGE_SLOAD, MSFV_STAGE_BLOCK_ADJ, MSFV_STAGE_FACE_ADJ, MSFV_STAGE_EDGE_ADJ,
+  MSFV_STAGE_GFINAL, MSFV_STAGE_RESIDUAL, MSFV_NSTAGE
+};
+
+typedef struct {
+  double ms[MSFV_NSTAGE];
+  int count[MSFV_NSTAGE];
+  unsigned long long work[8];
+} msfv_profile;
+
+msfv_status msfv_profile_enable(msfv_problem* p, int enable);
+msfv_status msfv_profile_read(msfv_problem* p, msfv_profile* out);
+const char* msfv_stage_name(int stage);
 
 const char* msfv_status_string(msfv_status s);
 const char* msfv_last_error(void);

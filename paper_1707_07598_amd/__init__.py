@@ -179,6 +179,25 @@ class Problem:
         _lib.check(self.lib.msfv_sync(self._h), "msfv_sync")
 
     # -- introspection -----------------------------------------------------
+    def profile_enable(self, enable: bool = True) -> None:
+        """Bracket every stage with HIP events on the problem's stream."""
+        _lib.check(self.lib.msfv_profile_enable(self._h, 1 if enable else 0), "msfv_profile_enable")
+
+    def profile_read(self) -> dict:
+        """Per-stage summed milliseconds and launch counts since the last
+        read, and the work counters; resets them."""
+        pr = _lib.MsfvProfile()
+        _lib.check(self.lib.msfv_profile_read(self._h, ctypes.byref(pr)), "msfv_profile_read")
+        stages = {}
+        for i in range(_lib.NSTAGE):
+            if pr.count[i]:
+                name = self.lib.msfv_stage_name(i).decode()
+                stages[name] = {"ms": pr.ms[i], "count": pr.count[i]}
+        work = {"block_fwd_cell_its": pr.work[0], "block_adj_cell_its": pr.work[1],
+                "face_fwd_cell_its": pr.work[2], "face_adj_cell_its": pr.work[3],
+                "coarse_fwd_row_its": pr.work[4], "coarse_adj_row_its": pr.work[5]}
+        return {"stages": stages, "work": work}
+
     def sizes(self) -> _lib.MsfvSizes:
         s = _lib.MsfvSizes()
         _lib.check(self.lib.msfv_get_sizes(self._h, ctypes.byref(s)), "msfv_get_sizes")

@@ -50,6 +50,14 @@ class MsfvStats(ctypes.Structure):
                 ("nonfinite", ctypes.c_int)]
 
 
+NSTAGE = 18
+
+
+class MsfvProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NSTAGE), ("count", ctypes.c_int * NSTAGE),
+                ("work", ctypes.c_ulonglong * 8)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _IP = ctypes.POINTER(ctypes.c_int)
@@ -69,6 +77,9 @@ SIGNATURES = {
     "msfv_get_prolongation": (_I, [_P, _IP, _IP, _DP]),
     "msfv_get_coarse": (_I, [_P, _IP, _IP, _DP, _DP]),
     "msfv_get_stats": (_I, [_P, ctypes.POINTER(MsfvStats)]),
+    "msfv_profile_enable": (_I, [_P, _I]),
+    "msfv_profile_read": (_I, [_P, ctypes.POINTER(MsfvProfile)]),
+    "msfv_stage_name": (ctypes.c_char_p, [_I]),
     "msfv_status_string": (ctypes.c_char_p, [_I]),
     "msfv_last_error": (ctypes.c_char_p, []),
 }

@@ -66,6 +66,25 @@ struct Columns {
   std::vector<double> val;
 };
 
+// Per-stage HIP events on the problem's stream (enabled by msfv_profile_enable).
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> recs;
+  hipEvent_t get() {
+    if (next < pool.size()) return pool[next++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+    ++next;
+    return e;
+  }
+  ~Profiler() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct msfv_problem {
@@ -97,6 +116,8 @@ struct msfv_problem {
 
   // coarse vectors (column j contiguous) and data scratch
   DevBuf<double> d_b, d_t, d_lam, d_D, d_v;
+  DevBuf<unsigned long long> d_work;
+  Profiler prof;
 
   size_t workspace_bytes() const {
     return d_edges.bytes() + d_faces.bytes() + d_blocks.bytes() + d_prow.bytes() + d_pcol.bytes() +
@@ -109,6 +130,22 @@ struct msfv_problem {
 };
 
 namespace {
+
+// Launch ``expr`` as stage ``id``; with profiling on, bracket it by events.
+#define STAGE(id, expr)                                                              \
+  do {                                                                               \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                         \
+    if (p->prof.on) {                                                                \
+      e0_ = p->prof.get();                                                           \
+      e1_ = p->prof.get();                                                           \
+      if (e0_) HIP_OK(hipEventRecord(e0_, p->stream));                               \
+    }                                                                                \
+    HIP_OK(expr);                                                                    \
+    if (p->prof.on && e0_ && e1_) {                                                  \
+      HIP_OK(hipEventRecord(e1_, p->stream));                                        \
+      p->prof.recs.emplace_back(id, e0_, e1_);                                       \
+    }                                                                                \
+  } while (0)
 
 msfv_status check_columns(const msfv_problem* p, int count, const int* ptr, const int* cell,
                           const double* val, Columns* out) {
@@ -292,11 +329,13 @@ msfv::LocalParams base_params(msfv_problem* p) {
   lp.eloc = p->d_eloc.ptr;
   lp.sload = p->d_sload.ptr;
   lp.W = p->d_W.ptr;
+  lp.work = p->d_work.ptr;
   return lp;
 }
 
 void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
   lp.nu_cap = nu_cap;
+  lp.sig_cap = c.closure;
   lp.lane_cap = c.lane;
   lp.col_cap = c.col;
   lp.nc_cap = c.nc;
@@ -317,43 +356,51 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   hipStream_t s = p->stream;
   const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   HIP_OK(hipMemsetAsync(p->d_status.ptr, 0, sizeof(int) * msfv::kStCount, s));
-  HIP_OK(hipMemcpyAsync(p->d_m.ptr, m, sizeof(double) * P.ncell, hipMemcpyDeviceToDevice, s));
-  HIP_OK(msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
+  STAGE(MSFV_STAGE_COPY_M,
+        hipMemcpyAsync(p->d_m.ptr, m, sizeof(double) * P.ncell, hipMemcpyDeviceToDevice, s));
+  STAGE(MSFV_STAGE_CHECK, msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
 
   msfv::LocalParams lp = base_params(p);
   lp.ents = p->d_edges.ptr;
   lp.nent = int(P.edges.size());
-  HIP_OK(msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
+  STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
 
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
   lp.nent = int(P.faces.size());
   set_caps(lp, P.caps_face, P.max_nu_face);
   lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
-  HIP_OK(msfv::launch_local_fwd(lp, 0, s));
+  lp.work_slot = 2;
+  STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_local_fwd(lp, 0, s));
 
   if (P.dim == 3) {
     lp = base_params(p);
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
     set_caps(lp, P.caps_block, P.max_nu_block);
-    HIP_OK(msfv::launch_local_fwd(lp, 0, s));
+    lp.work_slot = 0;
+    STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_local_fwd(lp, 0, s));
   }
-  HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
-                                p->d_kval.ptr, p->d_kdia.ptr, int(P.kcol.size()), s));
+  STAGE(MSFV_STAGE_KASSEMBLE,
+        msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
+                               p->d_kval.ptr, p->d_kdia.ptr, int(P.kcol.size()), s));
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
   HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
-  HIP_OK(msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
-                                   p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
-                                   p->nsrc_slot, 1, nc, s));
-  HIP_OK(msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_t.ptr, ns,
-                                 p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr, s));
-  HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
-                           p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
+  STAGE(MSFV_STAGE_COARSE_RHS,
+        msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
+                                  p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
+                                  p->nsrc_slot, 1, nc, s));
+  STAGE(MSFV_STAGE_COARSE_FWD,
+        msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_t.ptr, ns, p->cfg.coarse_rtol,
+                                p->cfg.coarse_maxit, p->d_status.ptr, p->d_work.ptr + 4, s));
+  STAGE(MSFV_STAGE_DATA,
+        msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
+                          p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
   if (u_out)
-    HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns,
-                                P.ncell, u_out, s));
+    STAGE(MSFV_STAGE_PROLONG,
+          msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns,
+                               P.ncell, u_out, s));
   p->have_forward = true;
   return MSFV_OK;
 }
@@ -366,14 +413,18 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
   HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
-  HIP_OK(msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
-                                   p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
-                                   p->nrec_slot, ns, nc, s));
-  HIP_OK(msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_lam.ptr, ns,
-                                 p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr, s));
-  HIP_OK(msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
-                            p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
-                            p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
+  STAGE(MSFV_STAGE_ADJ_RHS,
+        msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
+                                  p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
+                                  p->nrec_slot, ns, nc, s));
+  STAGE(MSFV_STAGE_COARSE_ADJ,
+        msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_lam.ptr, ns,
+                                p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr,
+                                p->d_work.ptr + 5, s));
+  STAGE(MSFV_STAGE_SLOAD,
+        msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
+                           p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
+                           p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
   msfv::LocalParams lp;
   if (P.dim == 3) {
     lp = base_params(p);
@@ -383,7 +434,8 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp.recv = p->d_faces.ptr;
     lp.push = lagrange ? 0 : 1;
     lp.solve_adj = 1;
-    HIP_OK(msfv::launch_local_adj(lp, 0, s));
+    lp.work_slot = 1;
+    STAGE(MSFV_STAGE_BLOCK_ADJ, msfv::launch_local_adj(lp, 0, s));
   }
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
@@ -392,13 +444,14 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp.recv = p->d_edges.ptr;
   lp.push = lagrange ? 0 : 1;
   lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
-  HIP_OK(msfv::launch_local_adj(lp, 0, s));
+  lp.work_slot = 3;
+  STAGE(MSFV_STAGE_FACE_ADJ, msfv::launch_local_adj(lp, 0, s));
 
   lp = base_params(p);
   lp.ents = p->d_edges.ptr;
   lp.nent = int(P.edges.size());
-  HIP_OK(msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
-  HIP_OK(msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
+  STAGE(MSFV_STAGE_EDGE_ADJ, msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
+  STAGE(MSFV_STAGE_GFINAL, msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
   return MSFV_OK;
 }
 
@@ -489,6 +542,8 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   HIP_OR_CLEAN(p->d_W.alloc(size_t(3) * P.ncell));
   HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
   HIP_OR_CLEAN(p->d_status.alloc(msfv::kStCount));
+  HIP_OR_CLEAN(p->d_work.alloc(8));
+  HIP_OR_CLEAN(hipMemsetAsync(p->d_work.ptr, 0, p->d_work.bytes(), s));
   HIP_OR_CLEAN(hipMemsetAsync(p->d_pval.ptr, 0, p->d_pval.bytes(), s));
   HIP_OR_CLEAN(hipMemsetAsync(p->d_inbuf.ptr, 0, p->d_inbuf.bytes(), s));
   HIP_OR_CLEAN(hipMemsetAsync(p->d_W.ptr, 0, p->d_W.bytes(), s));
@@ -555,7 +610,7 @@ msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_o
   st = forward_impl(p, m, p->d_D.ptr, nullptr);
   if (st != MSFV_OK) return st;
   const long long n = (long long)p->rec.count * p->src.count;
-  HIP_OK(msfv::launch_residual(p->d_D.ptr, d_obs, p->d_v.ptr, n, phi_out, p->stream));
+  STAGE(MSFV_STAGE_RESIDUAL, msfv::launch_residual(p->d_D.ptr, d_obs, p->d_v.ptr, n, phi_out, p->stream));
   return jtv_impl(p, p->d_v.ptr, g_out);
 }
 
@@ -607,6 +662,45 @@ msfv_status msfv_get_coarse(msfv_problem* p, int* row_ptr, int* col, double* val
     HIP_OK(hipMemcpy(t_out, p->d_t.ptr, size_t(P.ncoarse) * p->src.count * sizeof(double),
                      hipMemcpyDeviceToHost));
   return MSFV_OK;
+}
+
+msfv_status msfv_profile_enable(msfv_problem* p, int enable) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  p->prof.on = enable != 0;
+  p->prof.recs.clear();
+  p->prof.next = 0;
+  HIP_OK(hipMemset(p->d_work.ptr, 0, p->d_work.bytes()));
+  return MSFV_OK;
+}
+
+msfv_status msfv_profile_read(msfv_problem* p, msfv_profile* out) {
+  if (!p || !out) return fail(MSFV_EINVAL, "null argument");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  std::memset(out, 0, sizeof *out);
+  for (auto& r : p->prof.recs) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, std::get<1>(r), std::get<2>(r)));
+    const int id = std::get<0>(r);
+    if (id >= 0 && id < MSFV_NSTAGE) {
+      out->ms[id] += ms;
+      out->count[id] += 1;
+    }
+  }
+  p->prof.recs.clear();
+  p->prof.next = 0;
+  HIP_OK(hipMemcpy(out->work, p->d_work.ptr, sizeof out->work, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemset(p->d_work.ptr, 0, p->d_work.bytes()));
+  return MSFV_OK;
+}
+
+const char* msfv_stage_name(int stage) {
+  static const char* names[MSFV_NSTAGE] = {
+      "copy_m", "check_finite", "edge_fwd", "face_fwd", "block_fwd", "kassemble", "coarse_rhs",
+      "coarse_fwd", "data", "prolong", "adj_rhs", "coarse_adj", "sload", "block_adj",
+      "face_adj", "edge_adj", "gfinal", "residual"};
+  if (stage < 0 || stage >= MSFV_NSTAGE) return "unknown";
+  return names[stage];
 }
 
 msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out) {

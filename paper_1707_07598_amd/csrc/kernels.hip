@@ -352,6 +352,8 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
       const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
+      if (threadIdx.x == 0 && a.work)
+        atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu * ncp);
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -537,6 +539,8 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
       const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
+      if (threadIdx.x == 0 && a.work)
+        atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu * ncp);
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < CPT; ++j)
@@ -820,7 +824,8 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg_dia(const double* __restri
                                                           int ncx, int ncy, int ncz,
                                                           const double* __restrict__ rhs,
                                                           double* __restrict__ xout, double rtol,
-                                                          int maxit, int* status) {
+                                                          int maxit, int* status,
+                                                          unsigned long long* work) {
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
   const int nc = ncx * ncy * ncz;
@@ -921,6 +926,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg_dia(const double* __restri
   if (threadIdx.x == 0) {
     atomicMax(status + kStCoarseMaxIt, it);
     if (!ok) atomicAdd(status + kStCoarseNoconv, 1);
+    if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
   }
 }
 
@@ -1119,7 +1125,8 @@ int coarse_ldk(int nc) {
 }
 
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                             int ncol, double rtol, int maxit, int* status, hipStream_t s) {
+                             int ncol, double rtol, int maxit, int* status,
+                             unsigned long long* work, hipStream_t s) {
   if (ncol == 0) return hipSuccess;
   constexpr int B = 1024;
   const int nc = ncv[0] * ncv[1] * ncv[2];
@@ -1134,7 +1141,7 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
     if (lds > 64 * 1024)                                                                        \
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
     hipLaunchKernelGGL(kern, dim3(ncol), dim3(B), lds, s, kdia, ldk, ncv[0], ncv[1], ncv[2], rhs, x, \
-                       rtol, maxit, status);                                                    \
+                       rtol, maxit, status, work);                                              \
     return hipGetLastError();                                                                   \
   }
   MSFV_PCG_CASE(1)

@@ -57,6 +57,8 @@ struct LocalParams {
   double* W = nullptr;             // 3*N flux weights
   int solve_adj = 1;               // 0: flux-derivative (G) term only
   int push = 1;                    // 1: push loads to lower entities
+  unsigned long long* work = nullptr;  // work counters (cell-iterations)
+  int work_slot = 0;
 };
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
@@ -75,7 +77,8 @@ hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const int* dslot
 int coarse_ldk(int nc);
 // Jacobi-PCG on A_k with vertex 0 fixed, one workgroup per column of rhs.
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                             int ncol, double rtol, int maxit, int* status, hipStream_t s);
+                             int ncol, double rtol, int maxit, int* status,
+                             unsigned long long* work, hipStream_t s);
 // wave-per-corner local solves (wave_kernels.hip)
 bool wave_path_fits(const LocalParams& p);
 hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);

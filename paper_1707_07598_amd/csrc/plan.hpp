@@ -80,7 +80,7 @@ struct Plan {
   // geometry caps of a launch over faces or blocks (lane plane, column, corners,
   // zero-padded plane buffer); see the wave-per-corner kernels
   struct Caps {
-    int lane = 0, col = 0, nc = 0, plane = 0;
+    int lane = 0, col = 0, nc = 0, plane = 0, closure = 0;
   } caps_face, caps_block;
 
   // Build; returns an empty string on success or an error message.

@@ -289,6 +289,7 @@ __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[
 
 struct WaveLds {
   double* sig;
+  double* phi;   // basis values of the corners on the closure: phi[c*ncl + i]
   double* dsq;
   double* tt;    // 6 * nu (aliases pbuf)
   double* pbuf;  // NWAVE * plane_cap
@@ -300,13 +301,43 @@ template <int NWAVE>
 __device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
   WaveLds L;
   L.sig = lds;
-  L.dsq = L.sig + a.sig_cap;
+  L.phi = L.sig + a.sig_cap;
+  L.dsq = L.phi + 8 * a.sig_cap;
   L.Mm = L.dsq + a.nu_cap;
   L.Sm = L.Mm + 64;
   double* uni = L.Sm + 64;
   L.tt = uni;
   L.pbuf = uni;
   return L;
+}
+
+// Stage the S_k values of E's corners on E's closure into LDS (one coalesced
+// pass over the closure's CSR rows; corners that are not in a row read 0).
+template <int BLOCK>
+__device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* phi) {
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  const int nc = E.nc;
+  for (int i = threadIdx.x; i < ncl; i += BLOCK) {
+    const int lx = i % E.cext[0];
+    const int t = i / E.cext[0];
+    const int ly = t % E.cext[1];
+    const int lz = t / E.cext[1];
+    const int gid = (E.clo[0] + lx) + a.g.s1 * (E.clo[1] + ly) + a.g.s2 * (E.clo[2] + lz);
+    const int r0 = a.prow[gid], r1 = a.prow[gid + 1];
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = 0.0;
+    for (int e = r0; e < r1; ++e) {
+      const int vid = a.pcol[e];
+      const double val = a.pval[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nc && E.vid[q] == vid) v[q] = val;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nc) phi[q * ncl + i] = v[q];
+  }
 }
 
 // receiver-local own index of the neighbour across direction dd of cell (gcx, gcy, gcz)
@@ -330,6 +361,8 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
   const WaveLds S = carve<NWAVE>(a, lds);
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  load_phi_table<BLOCK>(E, a, S.phi);
   shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -341,7 +374,6 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
   __syncthreads();  // tt is dead from here on; pbuf aliases it
   double* pbuf = S.pbuf + wid * a.plane_cap;
   if (active) {
-    const int vid = E.vid[wid];
     double y[LMAX];
     if (!a.prescribe) {
       // scaled right-hand side: sum over Dirichlet neighbours T phi_c(n)
@@ -352,13 +384,12 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
         int fm, um;
         cell_masks(E, w, ia, ib, k, &fm, &um);
         const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-        const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
         double b = 0.0;
         for (int dd = 0; dd < 6; ++dd) {
           if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
           const int sgn = (dd & 1) ? 1 : -1;
-          const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
-          b += T * p_lookup(a.prow, a.pcol, a.pval, gid + sgn * axis_stride(w, dd >> 1, 1), vid);
+          const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
+          b += harm(S.sig[ci], S.sig[cn]) * S.phi[wid * ncl + cn];
         }
         y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
       }
@@ -367,6 +398,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
       if (lane == 0) {
         atomicMax(a.status + kStLocalMaxIt, it);
         if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+        if (a.work) atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu);
       }
       wave_sync_lds();
     }
@@ -400,7 +432,6 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
       int fm, um;
       cell_masks(E, w, ia, ib, k, &fm, &um);
       const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
       const int u = ia * w.ua + ib * w.ub + k * w.uc;
       for (int dd = 0; dd < 6; ++dd) {
         if (!((fm >> dd) & 1)) continue;
@@ -409,14 +440,14 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
         const int sgn = (dd & 1) ? 1 : -1;
         const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
         const int un = u + sgn * axis_stride(w, dd >> 1, 0);
-        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
+        const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
         double dp[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           dp[q] = 0.0;
           if (q >= nc) continue;
           const double pu = S.pbuf[q * a.plane_cap + u];
-          const double pn = own ? S.pbuf[q * a.plane_cap + un] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]);
+          const double pn = own ? S.pbuf[q * a.plane_cap + un] : S.phi[q * ncl + cn];
           dp[q] = pu - pn;
         }
         double dpc = 0.0;
@@ -447,6 +478,8 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
   const int nc = E.nc;
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  load_phi_table<BLOCK>(E, a, S.phi);
   shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
@@ -486,19 +519,15 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
       for (int e = E.eptr0; e < E.eptr1; ++e)
         if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
-      const int base = a.prow[gid];
       for (int dd = 0; dd < 6; ++dd) {
         if (!((fm >> dd) & 1)) continue;
         const bool own = (um >> dd) & 1;
         const int sgn = (dd & 1) ? 1 : -1;
-        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
+        const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
+        const double T = harm(S.sig[ci], S.sig[cn]);
         const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
-        const int nbase = a.prow[gn];
         double dy = 0.0;
-        for (int q = 0; q < nc; ++q) {
-          const double pn = own ? a.pval[nbase + q] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]);
-          dy += S.Sm[q * nc + c] * (a.pval[base + q] - pn);
-        }
+        for (int q = 0; q < nc; ++q) dy += S.Sm[q * nc + c] * (S.phi[q * ncl + ci] - S.phi[q * ncl + cn]);
         z -= T * dy;
         if (!own && a.push) {
           const int te = E.side_ent[dd];
@@ -519,6 +548,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     if (lane == 0) {
       atomicMax(a.status + kStLocalMaxIt, it);
       if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+      if (a.work) atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu);
     }
     wave_sync_lds();
     // mu_c into this wave's buffer; mu-part of the pushes
@@ -558,7 +588,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     cell_masks(E, w, ja, jb, k, &fm, &um);
     const int gid = w.g0 + ja * w.ga + jb * w.gb + k * w.gc;
     const int u = ja * w.ua + jb * w.ub + k * w.uc;
-    const int base = a.prow[gid];
+    const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
     for (int dd = 0; dd < 6; ++dd) {
       if (!((fm >> dd) & 1)) continue;
       const bool own = (um >> dd) & 1;
@@ -566,12 +596,10 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       const int sgn = (dd & 1) ? 1 : -1;
       const int un = u + sgn * axis_stride(w, dd >> 1, 0);
       const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
-      const int nbase = a.prow[gn];
+      const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
       double dp[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        dp[q] = q < nc ? a.pval[base + q] - (own ? a.pval[nbase + q] : p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]))
-                       : 0.0;
+      for (int q = 0; q < 8; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
       double wv = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -595,7 +623,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
 template <int NWAVE>
 size_t wave_lds_bytes(const LocalParams& p) {
   const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
-  return (size_t(p.sig_cap) + p.nu_cap + 128 + uni) * sizeof(double);
+  return (size_t(9) * p.sig_cap + p.nu_cap + 128 + uni) * sizeof(double);
 }
 
 template <int NWAVE, int LMAX>
