@@ -117,6 +117,11 @@ struct msfv_problem {
   // coarse vectors (column j contiguous) and data scratch
   DevBuf<double> d_b, d_t, d_lam, d_D, d_v;
   DevBuf<unsigned long long> d_work;
+  // per-entity CG statistics of the four local stages (block fwd, block adj,
+  // face fwd, face adj), at offsets ent_off[slot]
+  DevBuf<int> d_ent_it;
+  DevBuf<unsigned long long> d_ent_work;
+  int ent_off[5] = {0, 0, 0, 0, 0};
   Profiler prof;
 
   size_t workspace_bytes() const {
@@ -329,8 +334,21 @@ msfv::LocalParams base_params(msfv_problem* p) {
   lp.eloc = p->d_eloc.ptr;
   lp.sload = p->d_sload.ptr;
   lp.W = p->d_W.ptr;
-  lp.work = p->d_work.ptr;
   return lp;
+}
+
+// Route the per-entity statistics of local stage ``slot`` (0 block fwd,
+// 1 block adj, 2 face fwd, 3 face adj).
+void set_stats(msfv_problem* p, msfv::LocalParams& lp, int slot) {
+  lp.ent_it = p->d_ent_it.ptr + p->ent_off[slot];
+  lp.ent_work = p->d_ent_work.ptr + p->ent_off[slot];
+}
+
+// With profiling on, add the stage's cell-iterations to its work counter.
+hipError_t reduce_stats(msfv_problem* p, int slot, hipStream_t s) {
+  if (!p->prof.on) return hipSuccess;
+  return msfv::launch_reduce_work(p->d_ent_work.ptr + p->ent_off[slot],
+                                  p->ent_off[slot + 1] - p->ent_off[slot], p->d_work.ptr + slot, s);
 }
 
 void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
@@ -356,6 +374,7 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   hipStream_t s = p->stream;
   const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   HIP_OK(hipMemsetAsync(p->d_status.ptr, 0, sizeof(int) * msfv::kStCount, s));
+  HIP_OK(hipMemsetAsync(p->d_ent_it.ptr, 0, p->d_ent_it.bytes(), s));
   STAGE(MSFV_STAGE_COPY_M,
         hipMemcpyAsync(p->d_m.ptr, m, sizeof(double) * P.ncell, hipMemcpyDeviceToDevice, s));
   STAGE(MSFV_STAGE_CHECK, msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
@@ -370,16 +389,18 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   lp.nent = int(P.faces.size());
   set_caps(lp, P.caps_face, P.max_nu_face);
   lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
-  lp.work_slot = 2;
+  set_stats(p, lp, 2);
   STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_local_fwd(lp, 0, s));
+  HIP_OK(reduce_stats(p, 2, s));
 
   if (P.dim == 3) {
     lp = base_params(p);
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
     set_caps(lp, P.caps_block, P.max_nu_block);
-    lp.work_slot = 0;
+    set_stats(p, lp, 0);
     STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_local_fwd(lp, 0, s));
+    HIP_OK(reduce_stats(p, 0, s));
   }
   STAGE(MSFV_STAGE_KASSEMBLE,
         msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
@@ -434,8 +455,9 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp.recv = p->d_faces.ptr;
     lp.push = lagrange ? 0 : 1;
     lp.solve_adj = 1;
-    lp.work_slot = 1;
+    set_stats(p, lp, 1);
     STAGE(MSFV_STAGE_BLOCK_ADJ, msfv::launch_local_adj(lp, 0, s));
+    HIP_OK(reduce_stats(p, 1, s));
   }
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
@@ -444,8 +466,9 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp.recv = p->d_edges.ptr;
   lp.push = lagrange ? 0 : 1;
   lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
-  lp.work_slot = 3;
+  set_stats(p, lp, 3);
   STAGE(MSFV_STAGE_FACE_ADJ, msfv::launch_local_adj(lp, 0, s));
+  HIP_OK(reduce_stats(p, 3, s));
 
   lp = base_params(p);
   lp.ents = p->d_edges.ptr;
@@ -543,6 +566,15 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
   HIP_OR_CLEAN(p->d_status.alloc(msfv::kStCount));
   HIP_OR_CLEAN(p->d_work.alloc(8));
+  {
+    const int nb = int(P.blocks.size()), nf = int(P.faces.size());
+    const int cnt[4] = {nb, nb, nf, nf};
+    for (int k = 0; k < 4; ++k) p->ent_off[k + 1] = p->ent_off[k] + cnt[k];
+    HIP_OR_CLEAN(p->d_ent_it.alloc(std::max(1, p->ent_off[4])));
+    HIP_OR_CLEAN(p->d_ent_work.alloc(std::max(1, p->ent_off[4])));
+    HIP_OR_CLEAN(hipMemsetAsync(p->d_ent_it.ptr, 0, p->d_ent_it.bytes(), s));
+    HIP_OR_CLEAN(hipMemsetAsync(p->d_ent_work.ptr, 0, p->d_ent_work.bytes(), s));
+  }
   HIP_OR_CLEAN(hipMemsetAsync(p->d_work.ptr, 0, p->d_work.bytes(), s));
   HIP_OR_CLEAN(hipMemsetAsync(p->d_pval.ptr, 0, p->d_pval.bytes(), s));
   HIP_OR_CLEAN(hipMemsetAsync(p->d_inbuf.ptr, 0, p->d_inbuf.bytes(), s));
@@ -708,7 +740,12 @@ msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out) {
   HIP_OK(hipStreamSynchronize(p->stream));
   int st[msfv::kStCount];
   HIP_OK(hipMemcpy(st, p->d_status.ptr, sizeof st, hipMemcpyDeviceToHost));
-  out->local_max_it = st[msfv::kStLocalMaxIt];
+  std::vector<int> it(p->d_ent_it.n);
+  if (!it.empty())
+    HIP_OK(hipMemcpy(it.data(), p->d_ent_it.ptr, p->d_ent_it.bytes(), hipMemcpyDeviceToHost));
+  int itmax = 0;
+  for (int v : it) itmax = std::max(itmax, v);
+  out->local_max_it = itmax;
   out->local_noconv = st[msfv::kStLocalNoconv];
   out->coarse_max_it = st[msfv::kStCoarseMaxIt];
   out->coarse_noconv = st[msfv::kStCoarseNoconv];

@@ -320,6 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   }
   const double tol2 = a.rtol * a.rtol;
   int itmax = 0;
+  unsigned long long work = 0;
   bool all_ok = true;
   for (int c0 = 0; c0 < E.nc; c0 += NCP) {
     const int ncp = min(NCP, E.nc - c0);
@@ -352,8 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
       const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
-      if (threadIdx.x == 0 && a.work)
-        atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu * ncp);
+      work += (unsigned long long)it * E.nu * ncp;
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -364,9 +364,12 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
         if (c < ncp) a.pval[base + c] = x[j][c];
     }
   }
-  if (threadIdx.x == 0 && !a.prescribe) {
-    atomicMax(a.status + kStLocalMaxIt, itmax);
+  if (threadIdx.x == 0) {
     if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
+    if (a.ent_it) {
+      a.ent_it[blockIdx.x] = itmax;
+      a.ent_work[blockIdx.x] = work;
+    }
   }
   __syncthreads();  // S_k rows of this entity are visible to the workgroup
 
@@ -526,6 +529,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
   if (a.solve_adj) {
     const double tol2 = a.rtol * a.rtol;
     int itmax = 0;
+    unsigned long long work = 0;
     bool all_ok = true;
     for (int c0 = 0; c0 < nc; c0 += NCP) {
       const int ncp = min(NCP, nc - c0);
@@ -539,8 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
       const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
-      if (threadIdx.x == 0 && a.work)
-        atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu * ncp);
+      work += (unsigned long long)it * E.nu * ncp;
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < CPT; ++j)
@@ -605,8 +608,11 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
       }
     }
     if (threadIdx.x == 0) {
-      atomicMax(a.status + kStLocalMaxIt, itmax);
       if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
+      if (a.ent_it) {
+        a.ent_it[blockIdx.x] = itmax;
+        a.ent_work[blockIdx.x] = work;
+      }
     }
   }
   // flux weights of the fluxes this entity owns
@@ -797,6 +803,19 @@ __global__ void k_check_finite(const double* m, long long n, int* status) {
     if (!isfinite(v)) bad = true;
   }
   if (bad) atomicOr(status + kStNonfinite, 1);
+}
+
+__global__ void k_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work) {
+  __shared__ unsigned long long part[256];
+  unsigned long long acc = 0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += ent_work[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) work[0] += part[0];
 }
 
 __global__ void k_set_ones(const int* idx, int n, double* out) {
@@ -1102,6 +1121,13 @@ hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s) {
 
 hipError_t launch_local_fwd(const LocalParams& p, int, hipStream_t s) { return launch_local(p, false, s); }
 hipError_t launch_local_adj(const LocalParams& p, int, hipStream_t s) { return launch_local(p, true, s); }
+
+hipError_t launch_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_work, dim3(1), dim3(256), 0, s, ent_work, n, work);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;

@@ -18,7 +18,7 @@ struct GridInfo {
 enum StatusSlot {
   kStNonfinite = 0,
   kStLocalNoconv = 1,
-  kStLocalMaxIt = 2,
+  kStReserved = 2,  // local CG iteration counts are kept per entity
   kStCoarseNoconv = 3,
   kStCoarseMaxIt = 4,
   kStCount = 8
@@ -57,8 +57,8 @@ struct LocalParams {
   double* W = nullptr;             // 3*N flux weights
   int solve_adj = 1;               // 0: flux-derivative (G) term only
   int push = 1;                    // 1: push loads to lower entities
-  unsigned long long* work = nullptr;  // work counters (cell-iterations)
-  int work_slot = 0;
+  int* ent_it = nullptr;                  // per entity: largest CG iteration count of its corners
+  unsigned long long* ent_work = nullptr; // per entity: CG cell-iterations (iterations x own cells)
 };
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
@@ -66,6 +66,9 @@ hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s);
 hipError_t launch_local_fwd(const LocalParams& p, int kind_rmax, hipStream_t s);
 hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s);
 hipError_t launch_local_adj(const LocalParams& p, int kind_rmax, hipStream_t s);
+// work[0] += sum of ent_work[0..n) (one workgroup, fixed summation order)
+hipError_t launch_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work,
+                              hipStream_t s);
 hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s);
 // A_k as CSR (kval) and as 27 diagonals of the coarse grid (kdia[o*ldk + row],
 // o = (dx+1) + 3(dy+1) + 9(dz+1), ldk = coarse_ldk(nc)); dslot maps each CSR

@@ -28,10 +28,50 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
 
+// DPP lane exchange of a double within 16-lane rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wavefront sum, identical in every lane: exchange within quads (xor 1,
+// xor 2), half rows and rows by DPP, then add the four row sums read from
+// lanes 0, 16, 32, 48 in a fixed order.
 __device__ __forceinline__ double wsum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Block sum of N values per thread in a fixed order: wavefront sums, then
+// thread i adds the per-wave partials of value i in wave order.  On return
+// red[0..N) holds the sums, visible to every thread.  red holds NWAVE * N
+// doubles.
+template <int NWAVE, int N>
+__device__ __forceinline__ void block_sum(const double (&v)[N], double* red) {
+  const int wid = threadIdx.x / 64, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  for (int i = 0; i < N; ++i) {
+    const double t = wsum(v[i]);
+    if (lane == 0) red[wid * N + i] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = red[threadIdx.x];
+    for (int q = 1; q < NWAVE; ++q) t += red[q * N + threadIdx.x];
+    red[threadIdx.x] = t;  // only this thread touches column threadIdx.x
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -121,11 +161,24 @@ __device__ __forceinline__ void cell_masks(const EntDesc& E, const WGeo& w, int 
   *um = u & f;
 }
 
-__device__ __forceinline__ int axis_stride(const WGeo& w, int ax, int which) {
-  // which: 0 own-index, 1 global, 2 closure
-  if (ax == w.axa) return which == 0 ? w.ua : (which == 1 ? w.ga : w.sa);
-  if (ax == w.axb) return which == 0 ? w.ub : (which == 1 ? w.gb : w.sb);
-  return which == 0 ? w.uc : (which == 1 ? w.gc : w.sc);
+// Natural strides of global axis k in own-cell index space, closure space
+// and global cell space (k is a compile-time constant after unrolling).
+__device__ __forceinline__ int ustr(const EntDesc& E, int k) {
+  return k == 0 ? 1 : (k == 1 ? E.uext[0] : E.uext[0] * E.uext[1]);
+}
+__device__ __forceinline__ int cstr(const EntDesc& E, int k) {
+  return k == 0 ? 1 : (k == 1 ? E.cext[0] : E.cext[0] * E.cext[1]);
+}
+__device__ __forceinline__ int gstr(const GridInfo& g, int k) {
+  return k == 0 ? 1 : (k == 1 ? g.s1 : g.s2);
+}
+
+// global coordinates of the cell at lane position (ia, ib), column index k
+__device__ __forceinline__ void own_coords(const EntDesc& E, const WGeo& w, int ia, int ib, int k,
+                                           int gc[3]) {
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+    gc[ax] = sel3(ax, E.ulo[0], E.ulo[1], E.ulo[2]) + (ax == w.axa ? ia : (ax == w.axb ? ib : k));
 }
 
 // sigma on the closure, sqrt of the operator diagonal, scaled transmissibilities
@@ -152,7 +205,7 @@ __device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* 
 #pragma unroll
     for (int dd = 0; dd < 6; ++dd)
       if ((fm >> dd) & 1) {
-        const int st = axis_stride(w, dd >> 1, 2);
+        const int st = cstr(E, dd >> 1);
         d += harm(sig[ci], sig[ci + ((dd & 1) ? st : -st)]);
       }
     dsq[ia * w.ua + ib * w.ub + k * w.uc] = sqrt(d);
@@ -170,8 +223,8 @@ __device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* 
       double v = 0.0;
       if ((um >> dd) & 1) {
         const int sgn = (dd & 1) ? 1 : -1;
-        v = harm(sig[ci], sig[ci + sgn * axis_stride(w, dd >> 1, 2)]) /
-            (dsq[u] * dsq[u + sgn * axis_stride(w, dd >> 1, 0)]);
+        v = harm(sig[ci], sig[ci + sgn * cstr(E, dd >> 1)]) /
+            (dsq[u] * dsq[u + sgn * ustr(E, dd >> 1)]);
       }
       tt[dd * E.nu + u] = v;
     }
@@ -290,22 +343,32 @@ __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[
 struct WaveLds {
   double* sig;
   double* phi;   // basis values of the corners on the closure: phi[c*ncl + i]
+  double* ytab;  // adjoint: y_c = sum_q (M + M^T)_{qc} phi_q on the closure
   double* dsq;
   double* tt;    // 6 * nu (aliases pbuf)
   double* pbuf;  // NWAVE * plane_cap
   double* Mm;
   double* Sm;
+  int* wit;      // per wave: CG iterations of its corner
+  int* sbase;    // adjoint: per side d and corner c, offset of the receiver's load slot (-1: none)
+  int* sgeo;     // adjoint: per side, receiver-local index = gx + gy*s1 + gz*s2 + off: {s1, s2, off}
+  double* red;   // block reductions (8 waves x 36 values)
 };
 
 template <int NWAVE>
-__device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
+__device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds, bool adj) {
   WaveLds L;
   L.sig = lds;
   L.phi = L.sig + a.sig_cap;
-  L.dsq = L.phi + 8 * a.sig_cap;
+  L.ytab = L.phi + 8 * a.sig_cap;
+  L.dsq = L.ytab + (adj ? 8 * a.sig_cap : 0);
   L.Mm = L.dsq + a.nu_cap;
   L.Sm = L.Mm + 64;
-  double* uni = L.Sm + 64;
+  L.wit = reinterpret_cast<int*>(L.Sm + 64);
+  L.sbase = L.wit + 8;
+  L.sgeo = L.sbase + 48;
+  L.red = L.Sm + 64 + 40;
+  double* uni = L.red + 8 * 36;
   L.tt = uni;
   L.pbuf = uni;
   return L;
@@ -358,7 +421,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds);
+  const WaveLds S = carve<NWAVE>(a, lds, false);
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
@@ -385,10 +448,11 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
         cell_masks(E, w, ia, ib, k, &fm, &um);
         const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
         double b = 0.0;
+        #pragma unroll
         for (int dd = 0; dd < 6; ++dd) {
           if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
           const int sgn = (dd & 1) ? 1 : -1;
-          const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
+          const int cn = ci + sgn * cstr(E, dd >> 1);
           b += harm(S.sig[ci], S.sig[cn]) * S.phi[wid * ncl + cn];
         }
         y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
@@ -396,9 +460,8 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
       bool ok = true;
       const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
       if (lane == 0) {
-        atomicMax(a.status + kStLocalMaxIt, it);
+        S.wit[wid] = it;
         if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
-        if (a.work) atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu);
       }
       wave_sync_lds();
     }
@@ -422,49 +485,63 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
     }
   }
   __syncthreads();
-  // energy row K_E[c][:] = sum over the touched fluxes T dphi_c dphi^T
-  if (active) {
-    double acc[8];
+  if (threadIdx.x == 0 && a.ent_it) {
+    int itm = 0;
+    unsigned long long wk = 0;
+    if (!a.prescribe)
+      for (int q = 0; q < nc; ++q) {
+        itm = max(itm, S.wit[q]);
+        wk += (unsigned long long)S.wit[q] * E.nu;
+      }
+    a.ent_it[blockIdx.x] = itm;
+    a.ent_work[blockIdx.x] = wk;
+  }
+  // energy block K_E = sum over the touched fluxes T dphi dphi^T: one thread
+  // per own cell and its owned fluxes, then a fixed-order block reduction
+  constexpr int NQ = NWAVE * (NWAVE + 1) / 2;
+  double kacc[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int k = 0; k < w.L; ++k) {
-      if (!valid) break;
-      int fm, um;
-      cell_masks(E, w, ia, ib, k, &fm, &um);
-      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-      const int u = ia * w.ua + ib * w.ub + k * w.uc;
-      for (int dd = 0; dd < 6; ++dd) {
-        if (!((fm >> dd) & 1)) continue;
-        const bool own = (um >> dd) & 1;
-        if (!(dd & 1) && own) continue;  // counted from the lower own cell
-        const int sgn = (dd & 1) ? 1 : -1;
-        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
-        const int un = u + sgn * axis_stride(w, dd >> 1, 0);
-        const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
-        double dp[8];
+  for (int i = 0; i < NQ; ++i) kacc[i] = 0.0;
+  const int ncol = w.Ua * w.Ub;
+  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
+    const int col = i % ncol, k = i / ncol;
+    const int ja = col % w.Ua, jb = col / w.Ua;
+    int fm, um;
+    cell_masks(E, w, ja, jb, k, &fm, &um);
+    const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
+    const int u = ja * w.ua + jb * w.ub + k * w.uc;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          dp[q] = 0.0;
-          if (q >= nc) continue;
-          const double pu = S.pbuf[q * a.plane_cap + u];
-          const double pn = own ? S.pbuf[q * a.plane_cap + un] : S.phi[q * ncl + cn];
-          dp[q] = pu - pn;
-        }
-        double dpc = 0.0;
+    for (int dd = 0; dd < 6; ++dd) {
+      if (!((fm >> dd) & 1)) continue;
+      const bool own = (um >> dd) & 1;
+      if (!(dd & 1) && own) continue;  // counted from the lower own cell
+      const int sgn = (dd & 1) ? 1 : -1;
+      const int cn = ci + sgn * cstr(E, dd >> 1);
+      const int un = u + sgn * ustr(E, dd >> 1);
+      const double T = harm(S.sig[ci], S.sig[cn]);
+      double dp[NWAVE];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) dpc = (q == wid) ? dp[q] : dpc;
-        const double tc = T * dpc;
+      for (int q = 0; q < NWAVE; ++q) {
+        dp[q] = 0.0;
+        if (q >= nc) continue;
+        const double pn = own ? S.pbuf[q * a.plane_cap + un] : S.phi[q * ncl + cn];
+        dp[q] = S.pbuf[q * a.plane_cap + u] - pn;
+      }
+      int qq = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += tc * dp[q];
+      for (int q = 0; q < NWAVE; ++q) {
+        const double tq = T * dp[q];
+#pragma unroll
+        for (int q2 = q; q2 < NWAVE; ++q2) kacc[qq++] += tq * dp[q2];
       }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = wsum(acc[q]);
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nc) a.kent[E.kbase + wid * nc + q] = acc[q];
-    }
+  }
+  block_sum<NWAVE, NQ>(kacc, S.red);
+  // K_E[q][q2] from the upper triangle, row q at offset q*NWAVE - q(q-1)/2
+  if (threadIdx.x < nc * nc) {
+    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+    const int lo = min(q, q2), hi = max(q, q2);
+    a.kent[E.kbase + threadIdx.x] = S.red[lo * NWAVE - lo * (lo - 1) / 2 + (hi - lo)];
   }
 }
 
@@ -474,7 +551,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds);
+  const WaveLds S = carve<NWAVE>(a, lds, true);
   const int nc = E.nc;
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
@@ -492,6 +569,32 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
     S.Sm[threadIdx.x] = S.Mm[q * nc + q2] + S.Mm[q2 * nc + q];
+  }
+  // receiver slots of the pushes across each side of the closure
+  if (threadIdx.x < 48) {
+    const int side = threadIdx.x >> 3, c = threadIdx.x & 7;
+    const int te = E.side_ent[side];
+    int base = -1;
+    if (a.push && te >= 0 && c < nc) {
+      const EntDesc& R = a.recv[te];
+      const int ct = corner_in(R, E.vid[c]);
+      if (ct >= 0) base = R.inbase + (E.side_slot[side] * R.nc + ct) * R.nu;
+      if (c == 0) {
+        const int s1 = R.uext[0], s2 = R.uext[0] * R.uext[1];
+        S.sgeo[3 * side + 0] = s1;
+        S.sgeo[3 * side + 1] = s2;
+        S.sgeo[3 * side + 2] = -(R.ulo[0] + s1 * R.ulo[1] + s2 * R.ulo[2]);
+      }
+    }
+    S.sbase[threadIdx.x] = base;
+  }
+  __syncthreads();
+  // y_c on the closure
+  for (int i = threadIdx.x; i < ncl * nc; i += BLOCK) {
+    const int c = i / ncl, ci = i - c * ncl;
+    double v = 0.0;
+    for (int q = 0; q < nc; ++q) v += S.Sm[q * nc + c] * S.phi[q * ncl + ci];
+    S.ytab[c * ncl + ci] = v;
   }
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia = lane % w.Ua, ib = lane / w.Ua;
@@ -519,25 +622,24 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
       for (int e = E.eptr0; e < E.eptr1; ++e)
         if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
+      const double yu = S.ytab[c * ncl + ci];
+#pragma unroll
       for (int dd = 0; dd < 6; ++dd) {
         if (!((fm >> dd) & 1)) continue;
         const bool own = (um >> dd) & 1;
         const int sgn = (dd & 1) ? 1 : -1;
-        const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
+        const int cn = ci + sgn * cstr(E, dd >> 1);
         const double T = harm(S.sig[ci], S.sig[cn]);
-        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
-        double dy = 0.0;
-        for (int q = 0; q < nc; ++q) dy += S.Sm[q * nc + c] * (S.phi[q * ncl + ci] - S.phi[q * ncl + cn]);
+        const double dy = yu - S.ytab[c * ncl + cn];
         z -= T * dy;
-        if (!own && a.push) {
-          const int te = E.side_ent[dd];
-          if (te >= 0) {
-            const EntDesc& R = a.recv[te];
-            const int ct = corner_in(R, E.vid[c]);
-            if (ct >= 0) {
-              const int gx = gn % a.g.n[0], gy = (gn / a.g.n[0]) % a.g.n[1], gz = gn / (a.g.n[0] * a.g.n[1]);
-              a.outbuf[R.inbase + (E.side_slot[dd] * R.nc + ct) * R.nu + receiver_index(R, gx, gy, gz)] = T * dy;
-            }
+        if (!own) {
+          const int base = S.sbase[dd * 8 + c];
+          if (base >= 0) {
+            int gc3[3];
+            own_coords(E, w, ia, ib, k, gc3);
+            gc3[dd >> 1] += sgn;
+            a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
+                     S.sgeo[3 * dd + 2]] = T * dy;
           }
         }
       }
@@ -546,9 +648,8 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     bool ok = true;
     const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
     if (lane == 0) {
-      atomicMax(a.status + kStLocalMaxIt, it);
+      S.wit[wid] = it;
       if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
-      if (a.work) atomicAdd(a.work + a.work_slot, (unsigned long long)it * E.nu);
     }
     wave_sync_lds();
     // mu_c into this wave's buffer; mu-part of the pushes
@@ -562,23 +663,33 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       int fm, um;
       cell_masks(E, w, ia, ib, k, &fm, &um);
       const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+#pragma unroll
       for (int dd = 0; dd < 6; ++dd) {
         if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
-        const int te = E.side_ent[dd];
-        if (te < 0) continue;
-        const EntDesc& R = a.recv[te];
-        const int ct = corner_in(R, E.vid[c]);
-        if (ct < 0) continue;
+        const int base = S.sbase[dd * 8 + c];
+        if (base < 0) continue;
         const int sgn = (dd & 1) ? 1 : -1;
-        const double T = harm(S.sig[ci], S.sig[ci + sgn * axis_stride(w, dd >> 1, 2)]);
-        const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
-        const int gx = gn % a.g.n[0], gy = (gn / a.g.n[0]) % a.g.n[1], gz = gn / (a.g.n[0] * a.g.n[1]);
-        a.outbuf[R.inbase + (E.side_slot[dd] * R.nc + ct) * R.nu + receiver_index(R, gx, gy, gz)] += T * mu;
+        const double T = harm(S.sig[ci], S.sig[ci + sgn * cstr(E, dd >> 1)]);
+        int gc3[3];
+        own_coords(E, w, ia, ib, k, gc3);
+        gc3[dd >> 1] += sgn;
+        a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
+                 S.sgeo[3 * dd + 2]] += T * mu;
       }
     }
   }
   __syncthreads();
+  if (threadIdx.x == 0 && a.ent_it) {
+    int itm = 0;
+    unsigned long long wk = 0;
+    if (a.solve_adj)
+      for (int q = 0; q < nc; ++q) {
+        itm = max(itm, S.wit[q]);
+        wk += (unsigned long long)S.wit[q] * E.nu;
+      }
+    a.ent_it[blockIdx.x] = itm;
+    a.ent_work[blockIdx.x] = wk;
+  }
   // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for owned fluxes
   const int ncol = w.Ua * w.Ub;
   for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
@@ -589,14 +700,15 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     const int gid = w.g0 + ja * w.ga + jb * w.gb + k * w.gc;
     const int u = ja * w.ua + jb * w.ub + k * w.uc;
     const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
+    #pragma unroll
     for (int dd = 0; dd < 6; ++dd) {
       if (!((fm >> dd) & 1)) continue;
       const bool own = (um >> dd) & 1;
       if (!(dd & 1) && own) continue;
       const int sgn = (dd & 1) ? 1 : -1;
-      const int un = u + sgn * axis_stride(w, dd >> 1, 0);
-      const int gn = gid + sgn * axis_stride(w, dd >> 1, 1);
-      const int cn = ci + sgn * axis_stride(w, dd >> 1, 2);
+      const int un = u + sgn * ustr(E, dd >> 1);
+      const int gn = gid + sgn * gstr(a.g, dd >> 1);
+      const int cn = ci + sgn * cstr(E, dd >> 1);
       double dp[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
@@ -621,14 +733,14 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
 }
 
 template <int NWAVE>
-size_t wave_lds_bytes(const LocalParams& p) {
+size_t wave_lds_bytes(const LocalParams& p, bool adj) {
   const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
-  return (size_t(9) * p.sig_cap + p.nu_cap + 128 + uni) * sizeof(double);
+  return (size_t(adj ? 17 : 9) * p.sig_cap + p.nu_cap + 128 + 40 + 8 * 36 + uni) * sizeof(double);
 }
 
 template <int NWAVE, int LMAX>
 hipError_t launch_wave_t(const LocalParams& p, bool adj, hipStream_t s) {
-  const size_t lds = wave_lds_bytes<NWAVE>(p);
+  const size_t lds = wave_lds_bytes<NWAVE>(p, adj);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (adj) {
     auto kern = k_wave_adj<NWAVE, LMAX>;
