@@ -82,7 +82,17 @@ typedef struct {
   int local_maxit;    /* cap on local CG iterations (0: 1000)                */
   double coarse_rtol; /* coarse CG stop (0: 1e-13)                           */
   int coarse_maxit;   /* cap on coarse CG iterations (0: 20000)              */
+  int coarse_precond;  /* MSFV_COARSE_TWOLEVEL or MSFV_COARSE_JACOBI (below) */
 } msfv_config;
+
+/* Preconditioner of the coarse CG (same stop test and iteration cap either
+ * way; results agree to the coarse tolerance).
+ *   MSFV_COARSE_TWOLEVEL: Jacobi plus an additive correction on boxes of
+ *                         coarse vertices, M^-1 = D^-1 + Z (Z^T A Z)^-1 Z^T
+ *                         (at most 64 boxes); falls back to Jacobi where its
+ *                         tables do not fit in on-chip memory.
+ *   MSFV_COARSE_JACOBI  : M^-1 = D^-1.                                    */
+enum { MSFV_COARSE_TWOLEVEL = 0, MSFV_COARSE_JACOBI = 1 };
 
 typedef struct {
   long long ncell;     /* N                                                  */
@@ -163,7 +173,7 @@ enum {
   MSFV_STAGE_BLOCK_FWD, MSFV_STAGE_KASSEMBLE, MSFV_STAGE_COARSE_RHS, MSFV_STAGE_COARSE_FWD,
   MSFV_STAGE_DATA, MSFV_STAGE_PROLONG, MSFV_STAGE_ADJ_RHS, MSFV_STAGE_COARSE_ADJ,
   MSFV_STAGE_SLOAD, MSFV_STAGE_BLOCK_ADJ, MSFV_STAGE_FACE_ADJ, MSFV_STAGE_EDGE_ADJ,
-  MSFV_STAGE_GFINAL, MSFV_STAGE_RESIDUAL, MSFV_NSTAGE
+  MSFV_STAGE_GFINAL, MSFV_STAGE_RESIDUAL, MSFV_STAGE_COARSE_SETUP, MSFV_NSTAGE
 };
 
 typedef struct {

@@ -39,7 +39,7 @@ because the boundary values do not depend on m (Sec. 4.5).
 """
 from __future__ import annotations
 
-from typing import Dict, List
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import scipy.sparse as sp
@@ -166,17 +166,31 @@ def _lagrange_values(geom: Geometry, ent: Entity) -> np.ndarray:
     return out
 
 
-def build_basis(geom: Geometry, m: np.ndarray, mode: str = "reduced") -> Basis:
-    """S_k(m) (Sec. 3.2) for every coarse vertex."""
+def build_basis(geom: Geometry, m: np.ndarray, mode: str = "reduced",
+                only: Optional[Sequence[int]] = None) -> Basis:
+    """S_k(m) (Sec. 3.2) for every coarse vertex.
+
+    With ``only`` (indices into ``geom.entities``), just the rows of those
+    entities are built, together with the rows of every entity inside their
+    closures, which is all their boundary data depends on; other rows stay
+    empty.  Used to check single entities of grids too large to build whole.
+    """
     bas = Basis(geom, m, mode)
     for multi in geom.vertex_multis():
         cell = geom.vertex_cell(multi)
         bas.cols[cell, 0] = geom.vertex_id(multi)
         bas.vals[cell, 0] = 1.0
+    mark = None
+    if only is not None:
+        mark = np.zeros(geom.ncell, dtype=bool)
+        for i in only:
+            mark[geom.cell_ids(geom.entities[i].closure_ranges)] = True
     for idx, ent in enumerate(geom.entities):
         if ent.dim == 0:
             continue
         cells = geom.cell_ids(ent.cell_ranges)
+        if mark is not None and not mark[cells].all():
+            continue
         nc = len(ent.corners)
         if bas.solved(ent):
             lp = LocalProblem(geom, ent, bas.sigma)

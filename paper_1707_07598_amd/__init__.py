@@ -22,11 +22,13 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import MSFV_BC_LAGRANGE, MSFV_BC_REDUCED, MsfvError  # noqa: F401
+from ._lib import (MSFV_BC_LAGRANGE, MSFV_BC_REDUCED, MSFV_COARSE_JACOBI,  # noqa: F401
+                   MSFV_COARSE_TWOLEVEL, MsfvError)
 
 __all__ = ["Problem", "MSFVForward", "msfv_misfit", "MsfvError"]
 
 _MODES = {"reduced": MSFV_BC_REDUCED, "lagrange": MSFV_BC_LAGRANGE}
+_COARSE_PRECONDS = {"twolevel": MSFV_COARSE_TWOLEVEL, "jacobi": MSFV_COARSE_JACOBI}
 
 
 def _torch():
@@ -56,7 +58,7 @@ class Problem:
     def __init__(self, n: Sequence[int], r: Sequence[int], bc_mode: str = "reduced",
                  local_rtol: float = 1e-13, local_maxit: int = 1000,
                  coarse_rtol: float = 1e-13, coarse_maxit: int = 20000,
-                 device: int = 0, stream=None):
+                 coarse_precond: str = "twolevel", device: int = 0, stream=None):
         torch = _torch()
         self.lib = _lib.load()
         n = tuple(int(x) for x in n)
@@ -78,6 +80,9 @@ class Problem:
         cfg.local_maxit = local_maxit
         cfg.coarse_rtol = coarse_rtol
         cfg.coarse_maxit = coarse_maxit
+        if coarse_precond not in _COARSE_PRECONDS:
+            raise ValueError(f"coarse_precond must be one of {sorted(_COARSE_PRECONDS)}")
+        cfg.coarse_precond = _COARSE_PRECONDS[coarse_precond]
         self.bc_mode = bc_mode
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -21,6 +21,8 @@ MSFV_EDEVICE = -5
 MSFV_ESTATE = -6
 MSFV_BC_REDUCED = 0
 MSFV_BC_LAGRANGE = 1
+MSFV_COARSE_TWOLEVEL = 0
+MSFV_COARSE_JACOBI = 1
 
 STATUS_NAMES = {
     MSFV_OK: "MSFV_OK", MSFV_EINVAL: "MSFV_EINVAL", MSFV_ENOMEM: "MSFV_ENOMEM",
@@ -33,7 +35,7 @@ class MsfvConfig(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("r", ctypes.c_int * 3),
                 ("bc_mode", ctypes.c_int), ("local_rtol", ctypes.c_double),
                 ("local_maxit", ctypes.c_int), ("coarse_rtol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int)]
+                ("coarse_maxit", ctypes.c_int), ("coarse_precond", ctypes.c_int)]
 
 
 class MsfvSizes(ctypes.Structure):
@@ -50,7 +52,7 @@ class MsfvStats(ctypes.Structure):
                 ("nonfinite", ctypes.c_int)]
 
 
-NSTAGE = 18
+NSTAGE = 19
 
 
 class MsfvProfile(ctypes.Structure):

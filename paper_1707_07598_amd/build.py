@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmsfv.so")
 ARCH = os.environ.get("MSFV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "wave_kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "wave_kernels.hip", "coarse_kernels.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-result"]

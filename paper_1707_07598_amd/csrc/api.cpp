@@ -122,6 +122,9 @@ struct msfv_problem {
   DevBuf<int> d_ent_it;
   DevBuf<unsigned long long> d_ent_work;
   int ent_off[5] = {0, 0, 0, 0, 0};
+  // two-level coarse preconditioner: aggregates and (Z^T A_k Z)^-1
+  msfv::CoarseDefl defl;
+  DevBuf<double> d_einv;
   Profiler prof;
 
   size_t workspace_bytes() const {
@@ -130,7 +133,7 @@ struct msfv_problem {
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
-           d_sload.bytes();
+           d_sload.bytes() + d_einv.bytes();
   }
 };
 
@@ -360,6 +363,15 @@ void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
   lp.plane_cap = c.plane;
 }
 
+// Coarse solves of the ns columns of rhs with the configured preconditioner.
+hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned long long* work,
+                        hipStream_t s) {
+  const msfv::Plan& P = p->plan;
+  return msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
+                                 p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
+                                 p->d_status.ptr, work, s);
+}
+
 msfv_status ensure_ready(msfv_problem* p) {
   if (p->src.count <= 0) return fail(MSFV_ESTATE, "no sources set");
   if (p->rec.count <= 0) return fail(MSFV_ESTATE, "no receivers set");
@@ -405,6 +417,10 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   STAGE(MSFV_STAGE_KASSEMBLE,
         msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
                                p->d_kval.ptr, p->d_kdia.ptr, int(P.kcol.size()), s));
+  if (p->defl.ok)
+    STAGE(MSFV_STAGE_COARSE_SETUP,
+          msfv::launch_coarse_defl_setup(p->d_kdia.ptr, P.ncv, p->defl, p->d_einv.ptr,
+                                         p->d_status.ptr, s));
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
   HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
@@ -413,8 +429,7 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
                                   p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
                                   p->nsrc_slot, 1, nc, s));
   STAGE(MSFV_STAGE_COARSE_FWD,
-        msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_t.ptr, ns, p->cfg.coarse_rtol,
-                                p->cfg.coarse_maxit, p->d_status.ptr, p->d_work.ptr + 4, s));
+        coarse_solve(p, p->d_b.ptr, p->d_t.ptr, p->d_work.ptr + 4, s));
   STAGE(MSFV_STAGE_DATA,
         msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
                           p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
@@ -439,9 +454,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
                                   p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
                                   p->nrec_slot, ns, nc, s));
   STAGE(MSFV_STAGE_COARSE_ADJ,
-        msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, p->d_b.ptr, p->d_lam.ptr, ns,
-                                p->cfg.coarse_rtol, p->cfg.coarse_maxit, p->d_status.ptr,
-                                p->d_work.ptr + 5, s));
+        coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, p->d_work.ptr + 5, s));
   STAGE(MSFV_STAGE_SLOAD,
         msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
                            p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
@@ -511,6 +524,10 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   if (p->cfg.local_maxit <= 0) p->cfg.local_maxit = 1000;
   if (p->cfg.coarse_rtol <= 0) p->cfg.coarse_rtol = 1e-13;
   if (p->cfg.coarse_maxit <= 0) p->cfg.coarse_maxit = 20000;
+  if (p->cfg.coarse_precond != MSFV_COARSE_TWOLEVEL && p->cfg.coarse_precond != MSFV_COARSE_JACOBI) {
+    delete p;
+    return fail(MSFV_EINVAL, "coarse_precond must be MSFV_COARSE_TWOLEVEL or MSFV_COARSE_JACOBI");
+  }
   p->stream = static_cast<hipStream_t>(hip_stream);
   std::string err = p->plan.build(cfg->dim, cfg->n, cfg->r);
   if (!err.empty()) {
@@ -558,6 +575,13 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     HIP_OR_CLEAN(p->d_kdia.alloc(size_t(27) * ldk));
   }
   HIP_OR_CLEAN(hipMemsetAsync(p->d_kdia.ptr, 0, p->d_kdia.bytes(), s));
+  if (p->cfg.coarse_precond == MSFV_COARSE_TWOLEVEL) {
+    p->defl = msfv::coarse_defl_plan(P.ncv);
+    if (p->defl.ok) {
+      HIP_OR_CLEAN(p->d_einv.alloc(size_t(p->defl.na) * p->defl.na));
+      p->defl.einv = p->d_einv.ptr;
+    }
+  }
   HIP_OR_CLEAN(p->d_pval.alloc(P.pcol.size()));
   HIP_OR_CLEAN(p->d_kval.alloc(std::max<size_t>(1, P.kcol.size())));
   HIP_OR_CLEAN(p->d_kent.alloc(std::max<int64_t>(1, P.kent_size)));
@@ -730,7 +754,7 @@ const char* msfv_stage_name(int stage) {
   static const char* names[MSFV_NSTAGE] = {
       "copy_m", "check_finite", "edge_fwd", "face_fwd", "block_fwd", "kassemble", "coarse_rhs",
       "coarse_fwd", "data", "prolong", "adj_rhs", "coarse_adj", "sload", "block_adj",
-      "face_adj", "edge_adj", "gfinal", "residual"};
+      "face_adj", "edge_adj", "gfinal", "residual", "coarse_setup"};
   if (stage < 0 || stage >= MSFV_NSTAGE) return "unknown";
   return names[stage];
 }

@@ -1,0 +1,449 @@
+// Coarse solves of the pinned Galerkin system A_k t = S_k^T q (Sec. 3,
+// reduced forward problem) and of its transpose for the adjoint (Sec. 4.3).
+//
+// A_k is a 27-point stencil on the coarse-vertex grid, stored as 27 padded
+// diagonals.  One workgroup solves one right-hand side with preconditioned
+// CG: the search direction lives in LDS with a zero halo, so the stencil
+// loop is branch-free and every thread issues its coefficient loads back to
+// back.  Vertex 0 is fixed (t_0 = 0): its row and column drop out.
+//
+// Preconditioners:
+//  * Jacobi, M^-1 = D^-1;
+//  * two-level additive, M^-1 = D^-1 + Z E^-1 Z^T, with Z the indicator
+//    columns of boxes ("aggregates") of coarse vertices and E = Z^T A_k Z.
+//    E^-1 (at most 64 x 64) is formed once per operator by a setup kernel and
+//    kept in LDS by the solver.  On heterogeneous media this removes the
+//    slowest error components of the Jacobi iteration and cuts the
+//    iteration count by a factor of two or more.
+// All reductions (dot products, aggregate sums) run in a fixed order, so
+// results are bit-reproducible.
+#include "kernels.hpp"
+
+namespace msfv {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each 16-lane row (quad pairs, quads, half rows, rows); every lane
+// of the row ends with the same bits, since each step adds two equal-order
+// partials in either order.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double wsum(double v) {
+  v = row16_sum(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Sum NV values over the workgroup; every thread receives the totals (waves
+// added in a fixed order).  red holds NW * NV doubles and must not be reused
+// by the next call before every thread has read it (alternate two buffers).
+template <int NW, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wsum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = red[i];
+    for (int w = 1; w < NW; ++w) s += red[w * NV + i];
+    v[i] = s;
+  }
+}
+
+__device__ __forceinline__ int agg_index(const CoarseDefl& d, int x, int y, int z) {
+  return x / d.b[0] + d.na3[0] * (y / d.b[1] + d.na3[1] * (z / d.b[2]));
+}
+
+// out[a] = sum of stage over the vertices of aggregate a, 16 lanes per
+// aggregate, each lane striding over the box in a fixed order.
+template <int BLOCK>
+__device__ __forceinline__ void aggregate_sums(const double* stage, int ncx, int ncy, int ncz,
+                                               const CoarseDefl& d, double* out) {
+  const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int a = grp; a < d.na; a += BLOCK / 16) {
+    const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
+    const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
+    const int w = min(d.b[0], ncx - x0), h = min(d.b[1], ncy - y0), dz = min(d.b[2], ncz - z0);
+    const int cnt = w * h * dz;
+    double s = 0.0;
+    for (int k = l; k < cnt; k += 16) {
+      const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
+      s += stage[x + ncx * (y + ncy * z)];
+    }
+    s = row16_sum(s);
+    if (l == 0) out[a] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// E = Z^T A_k Z over the free vertices (vertex 0 excluded) and its inverse,
+// by one workgroup.  Assembly: 16 lanes per aggregate a; each lane walks its
+// share of the box's vertices and adds every stencil coefficient K_ij into
+// one of 27 accumulators, by the direction D from a to the aggregate of j
+// (each axis steps out of the box only from the box face on that side); the
+// 16-lane sums are E[a][a + D].  Inversion: Gauss-Jordan (E is SPD, so no
+// pivoting), lane = column, 16 waves sharing the rows, two barriers a step.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* __restrict__ kdia, int ldk,
+                                                             int ncx, int ncy, int ncz, CoarseDefl d,
+                                                             double* einv, int* status) {
+  extern __shared__ double lds[];
+  const int na = d.na;
+  double* E = lds;  // na * na, row-major
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int i = threadIdx.x; i < na * na; i += BLOCK) E[i] = 0.0;
+  __syncthreads();
+  const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int a = grp; a < na; a += BLOCK / 16) {
+    const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
+    const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
+    const int w = min(d.b[0], ncx - x0), h = min(d.b[1], ncy - y0), dd = min(d.b[2], ncz - z0);
+    const int cnt = w * h * dd;
+    double acc[27];
+#pragma unroll
+    for (int D = 0; D < 27; ++D) acc[D] = 0.0;
+    for (int k = l; k < cnt; k += 16) {
+      const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
+      const int i = x + ncx * (y + ncy * z);
+      if (i == 0) continue;
+      const bool lo[3] = {x == x0, y == y0, z == z0};
+      const bool hi[3] = {x == x0 + w - 1, y == y0 + h - 1, z == z0 + dd - 1};
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        if (i + ox + ncx * (oy + ncy * oz) == 0) continue;  // the fixed vertex
+        const double v = kdia[size_t(o) * ldk + i];
+        // aggregate step on each axis
+        const int sx = ox < 0 ? (lo[0] ? -1 : 0) : (ox > 0 ? (hi[0] ? 1 : 0) : 0);
+        const int sy = oy < 0 ? (lo[1] ? -1 : 0) : (oy > 0 ? (hi[1] ? 1 : 0) : 0);
+        const int sz = oz < 0 ? (lo[2] ? -1 : 0) : (oz > 0 ? (hi[2] ? 1 : 0) : 0);
+        // candidate directions of this offset: 0 or the offset's own step per axis
+#pragma unroll
+        for (int cz = 0; cz < (oz ? 2 : 1); ++cz)
+#pragma unroll
+          for (int cy = 0; cy < (oy ? 2 : 1); ++cy)
+#pragma unroll
+            for (int cx = 0; cx < (ox ? 2 : 1); ++cx) {
+              const int Dx = cx ? ox : 0, Dy = cy ? oy : 0, Dz = cz ? oz : 0;
+              const bool hit = sx == Dx && sy == Dy && sz == Dz;
+              acc[(Dx + 1) + 3 * (Dy + 1) + 9 * (Dz + 1)] += hit ? v : 0.0;
+            }
+      }
+    }
+#pragma unroll
+    for (int D = 0; D < 27; ++D) acc[D] = row16_sum(acc[D]);
+    if (l == 0) {
+#pragma unroll
+      for (int D = 0; D < 27; ++D) {
+        const int bx = ax + D % 3 - 1, by = ay + (D / 3) % 3 - 1, bz = az + D / 9 - 1;
+        if (bx >= 0 && bx < d.na3[0] && by >= 0 && by < d.na3[1] && bz >= 0 && bz < d.na3[2])
+          E[a * na + bx + d.na3[0] * (by + d.na3[1] * bz)] = acc[D];
+      }
+    }
+  }
+  __syncthreads();
+  const int j = threadIdx.x % kWave, rg = threadIdx.x / kWave;
+  constexpr int NRG = BLOCK / kWave;
+  for (int k = 0; k < na; ++k) {
+    const double piv = E[k * na + k];
+    const double inv = 1.0 / piv;
+    const double rk = j < na ? (j == k ? inv : E[k * na + j] * inv) : 0.0;
+    double f[64 / NRG];
+#pragma unroll
+    for (int t = 0; t < 64 / NRG; ++t) {
+      const int i = rg + t * NRG;
+      f[t] = i < na ? E[i * na + k] : 0.0;
+    }
+    if (threadIdx.x == 0 && !(piv > 0.0)) bad = 1;
+    __syncthreads();
+    if (j < na) {
+#pragma unroll
+      for (int t = 0; t < 64 / NRG; ++t) {
+        const int i = rg + t * NRG;
+        if (i >= na) continue;
+        if (i == k)
+          E[i * na + j] = rk;
+        else
+          E[i * na + j] = j == k ? -f[t] * inv : E[i * na + j] - f[t] * rk;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && bad) atomicAdd(status + kStCoarseNoconv, 1);
+  // symmetric part (the exact inverse is symmetric)
+  for (int t = threadIdx.x; t < na * na; t += BLOCK) {
+    const int r = t / na, c = t % na;
+    einv[t] = 0.5 * (E[r * na + c] + E[c * na + r]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG on the 27-diagonal operator, one workgroup per column.  Rows are padded
+// to ldk = RPT*BLOCK (padding rows have zero diagonals); the search direction
+// p lives in LDS with a zero halo of pad = 1 + Ncx + Ncx*Ncy entries on both
+// sides.  With DEFL, the LDS copy of p is reused between the stencil product
+// and the update of p to stage r for the aggregate sums.
+template <int BLOCK, int RPT, bool DEFL>
+__global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__ kdia, int ldk, int ncx,
+                                                      int ncy, int ncz, const double* __restrict__ rhs,
+                                                      double* __restrict__ xout, double rtol, int maxit,
+                                                      CoarseDefl d, int* status,
+                                                      unsigned long long* work) {
+  extern __shared__ double lds[];
+  constexpr int NW = BLOCK / kWave;
+  const int nc = ncx * ncy * ncz;
+  const int pad = 1 + ncx + ncx * ncy;
+  double* p = lds + pad;
+  double* redA = lds + ldk + 2 * pad;
+  double* redB = redA + NW * 4;
+  double* einv = redB + NW * 4;        // DEFL: na * na
+  double* sv = einv + (DEFL ? d.na * d.na : 0);  // DEFL: 64
+  double* yv = sv + 64;                // DEFL: 64
+  for (int i = threadIdx.x; i < ldk + 2 * pad; i += BLOCK) lds[i] = 0.0;
+  if (DEFL)
+    for (int i = threadIdx.x; i < d.na * d.na; i += BLOCK) einv[i] = d.einv[i];
+  __syncthreads();
+  const double* b = rhs + size_t(blockIdx.x) * nc;
+  double* xo = xout + size_t(blockIdx.x) * nc;
+  double x[RPT], r[RPT], pv[RPT], dinv[RPT];
+  unsigned agg[(RPT + 3) / 4];  // DEFL: aggregate of row q in byte q % 4 of agg[q / 4]
+#pragma unroll
+  for (int q = 0; q < (RPT + 3) / 4; ++q) agg[q] = 0u;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    x[q] = r[q] = pv[q] = dinv[q] = 0.0;
+    if (i >= nc || i == 0) continue;  // vertex 0 is fixed: its row and column drop out
+    const double dg = kdia[13 * ldk + i];
+    dinv[q] = dg > 0.0 ? 1.0 / dg : 0.0;
+    r[q] = b[i];
+    if (DEFL)
+      agg[q / 4] |= unsigned(agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy))) << (8 * (q % 4));
+  }
+
+  // Aggregate correction y = E^-1 Z^T r into yv (r staged in the LDS copy of
+  // p, which is free between the stencil product and the update of p).
+  auto coarse_correction = [&]() {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) p[threadIdx.x + q * BLOCK] = r[q];
+    __syncthreads();
+    aggregate_sums<BLOCK>(p, ncx, ncy, ncz, d, sv);
+    __syncthreads();
+    if (int(threadIdx.x) < d.na) {
+      double y = 0.0;
+      for (int c = 0; c < d.na; ++c) y += einv[c * d.na + threadIdx.x] * sv[c];
+      yv[threadIdx.x] = y;
+    }
+    __syncthreads();
+  };
+  // z = M^-1 r for row q (DEFL: after coarse_correction)
+  auto zrow = [&](int q) -> double {
+    double z = r[q] * dinv[q];
+    if (DEFL && dinv[q] != 0.0) z += yv[(agg[q / 4] >> (8 * (q % 4))) & 0xFFu];
+    return z;
+  };
+
+  if (DEFL) coarse_correction();
+  double s0[2] = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    pv[q] = zrow(q);
+    s0[0] += r[q] * r[q];
+    s0[1] += r[q] * pv[q];
+  }
+  block_sum<NW, 2>(s0, redA);  // its barrier also orders the staging reads before the writes below
+  const double bb = s0[0];
+  double rz = s0[1];
+  bool done = !(bb > 0.0);
+  const double tol2 = rtol * rtol;
+  const bool owns_pin = threadIdx.x == 0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) p[threadIdx.x + q * BLOCK] = pv[q];
+  __syncthreads();
+  int it = 0;
+  bool ok = true;
+  while (!done) {
+    if (it >= maxit) {
+      ok = false;
+      break;
+    }
+    ++it;
+    double ap[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) ap[q] = 0.0;
+    // Opaque copies of the uniform base and the lane offset: the 27*RPT
+    // coefficient addresses are formed here (scalar base + one lane offset)
+    // instead of being hoisted out of the loop and spilled.
+    const double* kb = kdia;
+    int lo = threadIdx.x;
+    asm volatile("" : "+s"(kb));
+    asm volatile("" : "+v"(lo));
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+          const int off = dx + ncx * (dy + ncy * dz);
+          const double* kd = kb + size_t(o) * ldk;
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) ap[q] += kd[q * BLOCK + lo] * p[lo + q * BLOCK + off];
+        }
+    if (owns_pin) ap[0] = 0.0;
+    double pq[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) pq[0] += pv[q] * ap[q];
+    block_sum<NW, 1>(pq, redA);  // also: every thread is past its stencil reads of p
+    const double alpha = pq[0] != 0.0 ? rz / pq[0] : 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      x[q] += alpha * pv[q];
+      r[q] -= alpha * ap[q];
+    }
+    if (DEFL) coarse_correction();
+    double s2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      s2[0] += r[q] * r[q];
+      s2[1] += r[q] * zrow(q);
+    }
+    block_sum<NW, 2>(s2, redB);
+    if (s2[0] <= tol2 * bb) break;
+    if (s2[0] != s2[0]) {
+      ok = false;
+      break;
+    }
+    const double beta = rz != 0.0 ? s2[1] / rz : 0.0;
+    rz = s2[1];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      pv[q] = zrow(q) + beta * pv[q];
+      p[threadIdx.x + q * BLOCK] = pv[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    if (i < nc) xo[i] = x[q];
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(status + kStCoarseMaxIt, it);
+    if (!ok) atomicAdd(status + kStCoarseNoconv, 1);
+    if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
+  }
+}
+
+constexpr int kBlock = 1024;
+
+size_t pcg_lds_bytes(int ldk, int pad, int na) {
+  return (size_t(ldk) + 2 * pad + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128) * sizeof(double);
+}
+
+size_t setup_lds_bytes(int na) { return size_t(na) * na * sizeof(double); }
+
+}  // namespace
+
+int coarse_ldk(int nc) {
+  const int rpt = (nc + kBlock - 1) / kBlock;
+  const int r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : 16;
+  return r * kBlock;
+}
+
+CoarseDefl coarse_defl_plan(const int ncv[3]) {
+  CoarseDefl d;
+  for (int k = 0; k < 3; ++k) d.b[k] = std::min(4, std::max(1, ncv[k]));
+  auto count = [&](int k) { return (ncv[k] + d.b[k] - 1) / d.b[k]; };
+  for (;;) {
+    for (int k = 0; k < 3; ++k) d.na3[k] = count(k);
+    d.na = d.na3[0] * d.na3[1] * d.na3[2];
+    if (d.na <= 64) break;
+    int kmax = 0;
+    for (int k = 1; k < 3; ++k)
+      if (d.na3[k] > d.na3[kmax]) kmax = k;
+    d.b[kmax] *= 2;
+  }
+  const int nc = ncv[0] * ncv[1] * ncv[2];
+  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  d.ok = d.na >= 2 && pcg_lds_bytes(coarse_ldk(nc), pad, d.na) <= 160 * 1024 &&
+         setup_lds_bytes(d.na) <= 160 * 1024;
+  return d;
+}
+
+hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
+                                    double* einv, int* status, hipStream_t s) {
+  if (!d.ok) return hipErrorInvalidConfiguration;
+  const int nc = ncv[0] * ncv[1] * ncv[2];
+  const size_t lds = setup_lds_bytes(d.na);
+  auto kern = k_coarse_defl_setup<kBlock>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(1), dim3(kBlock), lds, s, kdia, coarse_ldk(nc), ncv[0], ncv[1],
+                     ncv[2], d, einv, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
+                             int ncol, double rtol, int maxit, const CoarseDefl* defl, int* status,
+                             unsigned long long* work, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  const int nc = ncv[0] * ncv[1] * ncv[2];
+  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  const int ldk = coarse_ldk(nc);
+  const bool use = defl && defl->ok && defl->einv;
+  const CoarseDefl d = use ? *defl : CoarseDefl();
+  const size_t lds = pcg_lds_bytes(ldk, pad, use ? d.na : 0);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const int rpt = ldk / kBlock;
+#define MSFV_PCG_CASE(R)                                                                          \
+  if (rpt <= R) {                                                                                 \
+    auto kern = use ? k_coarse_pcg<kBlock, R, true> : k_coarse_pcg<kBlock, R, false>;             \
+    if (lds > 64 * 1024) {                                                                        \
+      hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));   \
+      if (e != hipSuccess) return e;                                                              \
+    }                                                                                             \
+    hipLaunchKernelGGL(kern, dim3(ncol), dim3(kBlock), lds, s, kdia, ldk, ncv[0], ncv[1], ncv[2], \
+                       rhs, x, rtol, maxit, d, status, work);                                     \
+    return hipGetLastError();                                                                     \
+  }
+  MSFV_PCG_CASE(1)
+  MSFV_PCG_CASE(2)
+  MSFV_PCG_CASE(4)
+  MSFV_PCG_CASE(8)
+  MSFV_PCG_CASE(16)
+#undef MSFV_PCG_CASE
+  return hipErrorInvalidConfiguration;
+}
+
+}  // namespace msfv

@@ -833,122 +833,6 @@ __global__ void k_kassemble(const int* kcptr, const int* kcidx, const int* dslot
   kdia[dslot[i]] = s;
 }
 
-// Jacobi-PCG on the 27-diagonal coarse operator; one workgroup per column.
-// Rows are padded to ldk = RPT*BLOCK (padding rows have zero diagonals), and
-// search directions live in LDS with a zero halo of pad = 1 + Ncx + Ncx*Ncy
-// entries on both sides, so the stencil loop has no branches: every thread
-// issues its 27*RPT independent coefficient loads back to back.
-template <int BLOCK, int RPT>
-__global__ __launch_bounds__(BLOCK) void k_coarse_pcg_dia(const double* __restrict__ kdia, int ldk,
-                                                          int ncx, int ncy, int ncz,
-                                                          const double* __restrict__ rhs,
-                                                          double* __restrict__ xout, double rtol,
-                                                          int maxit, int* status,
-                                                          unsigned long long* work) {
-  extern __shared__ double lds[];
-  constexpr int NW = BLOCK / kWave;
-  const int nc = ncx * ncy * ncz;
-  const int pad = 1 + ncx + ncx * ncy;
-  double* p = lds + pad;
-  double* redA = lds + ldk + 2 * pad;
-  double* redB = redA + NW * 4;
-  for (int i = threadIdx.x; i < ldk + 2 * pad; i += BLOCK) lds[i] = 0.0;
-  __syncthreads();
-  const double* b = rhs + size_t(blockIdx.x) * nc;
-  double* xo = xout + size_t(blockIdx.x) * nc;
-  double x[RPT], r[RPT], pv[RPT], dinv[RPT];
-  double sums[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int i = threadIdx.x + q * BLOCK;
-    x[q] = r[q] = pv[q] = dinv[q] = 0.0;
-    if (i >= nc || i == 0) continue;  // vertex 0 is fixed: its row and column drop out
-    const double dg = kdia[13 * ldk + i];
-    dinv[q] = dg > 0.0 ? 1.0 / dg : 0.0;
-    r[q] = b[i];
-    pv[q] = r[q] * dinv[q];
-    sums[0] += r[q] * r[q];
-    sums[1] += r[q] * pv[q];
-    p[i] = pv[q];
-  }
-  block_sum<NW, 3>(sums, 2, redA);
-  const double bb = sums[0];
-  double rz = sums[1];
-  bool done = !(bb > 0.0);
-  const double tol2 = rtol * rtol;
-  const bool owns_pin = threadIdx.x == 0;
-  __syncthreads();
-  int it = 0;
-  bool ok = true;
-  while (!done) {
-    if (it >= maxit) {
-      ok = false;
-      break;
-    }
-    ++it;
-    double ap[RPT];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) ap[q] = 0.0;
-    // Opaque copies of the uniform base and the lane offset: the 27*RPT
-    // coefficient addresses are formed here (scalar base + one lane offset)
-    // instead of being hoisted out of the loop and spilled.
-    const double* kb = kdia;
-    int lo = threadIdx.x;
-    asm volatile("" : "+s"(kb));
-    asm volatile("" : "+v"(lo));
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-          const int off = dx + ncx * (dy + ncy * dz);
-          const double* kd = kb + size_t(o) * ldk;
-#pragma unroll
-          for (int q = 0; q < RPT; ++q) ap[q] += kd[q * BLOCK + lo] * p[lo + q * BLOCK + off];
-        }
-    if (owns_pin) ap[0] = 0.0;
-    double pq[1] = {0.0};
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) pq[0] += pv[q] * ap[q];
-    block_sum<NW, 1>(pq, 1, redA);
-    const double alpha = pq[0] != 0.0 ? rz / pq[0] : 0.0;
-    double s2[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      x[q] += alpha * pv[q];
-      r[q] -= alpha * ap[q];
-      s2[0] += r[q] * r[q];
-      s2[1] += r[q] * r[q] * dinv[q];
-    }
-    block_sum<NW, 3>(s2, 2, redB);
-    if (s2[0] <= tol2 * bb) break;
-    if (s2[0] != s2[0]) {
-      ok = false;
-      break;
-    }
-    const double beta = rz != 0.0 ? s2[1] / rz : 0.0;
-    rz = s2[1];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      pv[q] = r[q] * dinv[q] + beta * pv[q];
-      p[threadIdx.x + q * BLOCK] = pv[q];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int i = threadIdx.x + q * BLOCK;
-    if (i < nc) xo[i] = x[q];
-  }
-  if (threadIdx.x == 0) {
-    atomicMax(status + kStCoarseMaxIt, it);
-    if (!ok) atomicAdd(status + kStCoarseNoconv, 1);
-    if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
-  }
-}
-
 __global__ void k_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,
                                const double* ent_w, const int* ent_col, const double* colw,
                                int colw_ld, const double* pval, double* out, int nslot, int ncol,
@@ -1141,42 +1025,6 @@ hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const int* dslot
   hipLaunchKernelGGL(k_kassemble, dim3((nnz + 255) / 256), dim3(256), 0, s, kcptr, kcidx, dslot, kent,
                      kval, kdia, nnz);
   return hipGetLastError();
-}
-
-int coarse_ldk(int nc) {
-  constexpr int B = 1024;
-  const int rpt = (nc + B - 1) / B;
-  const int r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : 16;
-  return r * B;
-}
-
-hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                             int ncol, double rtol, int maxit, int* status,
-                             unsigned long long* work, hipStream_t s) {
-  if (ncol == 0) return hipSuccess;
-  constexpr int B = 1024;
-  const int nc = ncv[0] * ncv[1] * ncv[2];
-  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
-  const int ldk = coarse_ldk(nc);
-  const size_t lds = (size_t(ldk) + 2 * pad + 2 * (B / kWave) * 4) * sizeof(double);
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  const int rpt = ldk / B;
-#define MSFV_PCG_CASE(R)                                                                        \
-  if (rpt <= R) {                                                                               \
-    auto kern = k_coarse_pcg_dia<B, R>;                                                         \
-    if (lds > 64 * 1024)                                                                        \
-      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
-    hipLaunchKernelGGL(kern, dim3(ncol), dim3(B), lds, s, kdia, ldk, ncv[0], ncv[1], ncv[2], rhs, x, \
-                       rtol, maxit, status, work);                                              \
-    return hipGetLastError();                                                                   \
-  }
-  MSFV_PCG_CASE(1)
-  MSFV_PCG_CASE(2)
-  MSFV_PCG_CASE(4)
-  MSFV_PCG_CASE(8)
-  MSFV_PCG_CASE(16)
-#undef MSFV_PCG_CASE
-  return hipErrorInvalidConfiguration;
 }
 
 hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,

@@ -1,9 +1,11 @@
 // Launchers of the gfx950 kernels of the MSFV path (implemented in
-// kernels.hip).  All pointers are device pointers; every launcher enqueues
+// kernels.hip, wave_kernels.hip and coarse_kernels.hip).  All pointers are device pointers; every launcher enqueues
 // on ``stream`` and returns the hipError_t of the launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "plan.hpp"
 
@@ -78,9 +80,24 @@ hipError_t launch_kassemble(const int* kcptr, const int* kcidx, const int* dslot
 // Row stride of the diagonal storage used by the coarse solver (rows padded
 // with zeros to a multiple of its workgroup size).
 int coarse_ldk(int nc);
-// Jacobi-PCG on A_k with vertex 0 fixed, one workgroup per column of rhs.
+// Aggregates of the two-level coarse preconditioner: boxes of b[0] x b[1] x
+// b[2] coarse vertices, na3[k] boxes per axis, na <= 64 in all.
+struct CoarseDefl {
+  int b[3] = {1, 1, 1};
+  int na3[3] = {1, 1, 1};
+  int na = 0;
+  bool ok = false;              // fits the kernels' LDS budgets
+  const double* einv = nullptr; // device, na x na: (Z^T A_k Z)^-1 over the free vertices
+};
+CoarseDefl coarse_defl_plan(const int ncv[3]);
+// einv = (Z^T A_k Z)^-1 (one workgroup); a non-positive pivot counts as a
+// non-converged coarse solve in status.
+hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
+                                    double* einv, int* status, hipStream_t s);
+// PCG on A_k with vertex 0 fixed, one workgroup per column of rhs; Jacobi
+// preconditioned, plus the aggregate correction when defl is given.
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                             int ncol, double rtol, int maxit, int* status,
+                             int ncol, double rtol, int maxit, const CoarseDefl* defl, int* status,
                              unsigned long long* work, hipStream_t s);
 // wave-per-corner local solves (wave_kernels.hip)
 bool wave_path_fits(const LocalParams& p);

@@ -1,0 +1,161 @@
+"""Parity at the full workload sizes.
+
+* 64^3, r = 8, 16 surface dipoles, 256 receivers: D, t and the gradient
+  element-wise against the oracle (same bars as the small cases).
+* 128^3, r = 8, 32 surface dipoles, 1024 receivers, in the launch
+  configuration the benchmark times (automatic coarse mode, every stage on
+  the device): sampled basis rows and coarse-operator rows against the
+  oracle, which builds just the entities involved; then properties that
+  hold at any size: the pinned coarse residual, symmetry and zero row sums
+  of A_k (Sec. 3, S_k 1 = 1 and A 1 = 0), a central finite difference of the
+  misfit along a random direction, and bit-identical repeated evaluations.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import Geometry
+from oracle import reduced as R
+from oracle.basis import build_basis
+from oracle.operator import fine_faces
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _problem(inst, **kw):
+    import paper_1707_07598_amd as msfv
+    prob = msfv.Problem(inst.n, inst.r, "reduced", **kw)
+    prob.set_sources(inst.sources)
+    prob.set_receivers(inst.receivers)
+    return prob
+
+
+def test_workload_64_parity():
+    import torch
+    inst = W.workload_64()
+    g = Geometry(inst.n, inst.r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers)
+    Dobs = R.forward(g, inst.m_obs, inst.sources, inst.receivers).D
+    g_ref = R.jtv(st, st.D - Dobs)
+    prob = _problem(inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    D = prob.forward(m).cpu().numpy()
+    _, t = prob.coarse()
+    gg = prob.jtv(torch.tensor((st.D - Dobs).T.copy(), dtype=torch.float64, device="cuda"))
+    assert _rel(D, st.D.T) < 1e-10
+    assert _rel(t, st.t.T) < 1e-10
+    assert _rel(gg.cpu().numpy(), g_ref) < 1e-8
+    prob.close()
+
+
+@pytest.fixture(scope="module")
+def full128():
+    import torch
+    inst = W.workload_128()
+    prob = _problem(inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    d_obs = prob.forward(torch.tensor(inst.m_obs, dtype=torch.float64, device="cuda")).clone()
+    phi, grad = prob.misfit_grad(m, d_obs)
+    out = {"inst": inst, "prob": prob, "m": m, "d_obs": d_obs, "phi": phi.item(),
+           "grad": grad.clone(), "stats": prob.stats()}
+    rp, col, val = prob.prolongation()
+    out["P"] = sp.csr_matrix((val, col, rp), shape=(int(np.prod(inst.n)), prob.sizes().ncoarse))
+    (krp, kcol, kval), t = prob.coarse()
+    out["K"] = sp.csr_matrix((kval, kcol, krp), shape=(prob.sizes().ncoarse,) * 2)
+    out["t"] = t
+    out["geom"] = Geometry(inst.n, inst.r)
+    yield out
+    prob.close()
+
+
+def _owner(g):
+    own = -np.ones(g.ncell, dtype=np.int64)
+    for i, e in enumerate(g.entities):
+        own[g.cell_ids(e.cell_ranges)] = i
+    return own
+
+
+def test_128_sampled_basis_rows(full128):
+    g, inst, P = full128["geom"], full128["inst"], full128["P"]
+    rng = np.random.default_rng(21)
+    picks = []
+    for d in (1, 2, 3):
+        cand = [i for i, e in enumerate(g.entities) if e.dim == d]
+        picks += [cand[0], cand[-1]] + list(rng.choice(cand, 3, replace=False))
+    bas = build_basis(g, inst.m, "reduced", only=picks)
+    Pref = bas.csr()
+    for i in picks:
+        cells = g.cell_ids(g.entities[i].cell_ranges)
+        a = P[cells].toarray()
+        b = Pref[cells].toarray()
+        assert np.abs(a - b).max() < 1e-10, (i, g.entities[i].dim)
+    assert full128["stats"].local_noconv == 0
+
+
+def test_128_sampled_coarse_rows(full128):
+    g, inst, K = full128["geom"], full128["inst"], full128["K"]
+    own = _owner(g)
+    a, b, T, _, _ = fine_faces(g, inst.m)
+    rng = np.random.default_rng(22)
+    nc = g.ncoarse
+    top = [g.vertex_id((i, j, 0)) for i in range(g.nc[0]) for j in range(g.nc[1])]
+    vids = [0, nc - 1, int(rng.choice(top)), int(rng.integers(1, nc - 1))]
+    for I in vids:
+        # S_k column I lives on the entities with corner I; the fluxes that
+        # see it reach one cell further
+        sup = np.zeros(g.ncell, dtype=bool)
+        for e in g.entities:
+            if I in e.corners:
+                sup[g.cell_ids(e.cell_ranges)] = True
+        ring = sup.copy()
+        ring[a[sup[b]]] = True
+        ring[b[sup[a]]] = True
+        only = np.unique(own[ring])
+        Pr = build_basis(g, inst.m, "reduced", only=list(only)).csr()
+        sel = sup[a] | sup[b]
+        dP = (Pr[a[sel]] - Pr[b[sel]]).tocsc()
+        dPI = dP[:, I].toarray().ravel()
+        row_ref = np.asarray(dP.T @ (T[sel] * dPI)).ravel()
+        row = K[I].toarray().ravel()
+        assert _rel(row, row_ref) < 1e-10, I
+
+
+def test_128_coarse_residual_and_invariants(full128):
+    inst, P, K, t = full128["inst"], full128["P"], full128["K"], full128["t"]
+    n = int(np.prod(inst.n))
+    Q = R.columns_matrix(n, inst.sources)
+    B = np.asarray((P.T @ Q).todense())          # (Nc, Ns)
+    Kp = K[1:, 1:]
+    res = Kp @ t[:, 1:].T - B[1:]
+    assert np.all(t[:, 0] == 0.0)
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(B[1:]) * 10
+    d = K.diagonal()
+    assert (d > 0).all()
+    assert abs(K - K.T).max() <= 1e-12 * d.max()
+    assert np.abs(np.asarray(K.sum(axis=1)).ravel()).max() <= 1e-11 * d.max()
+    # S_k 1 = 1 on every fine cell
+    assert np.abs(np.asarray(P.sum(axis=1)).ravel() - 1.0).max() < 1e-12
+
+
+def test_128_gradient_fd_and_determinism(full128):
+    import torch
+    prob, m, d_obs = full128["prob"], full128["m"], full128["d_obs"]
+    grad = full128["grad"]
+    e = torch.tensor(np.random.default_rng(23).standard_normal(m.numel()), device="cuda")
+    h = 1e-5
+    fp, _ = prob.misfit_grad(m + h * e, d_obs)
+    fm, _ = prob.misfit_grad(m - h * e, d_obs)
+    fd = (fp.item() - fm.item()) / (2 * h)
+    dd = (grad * e).sum().item()
+    assert abs(fd - dd) <= 1e-5 * abs(dd)
+    phi2, grad2 = prob.misfit_grad(m, d_obs)
+    assert phi2.item() == full128["phi"]
+    assert torch.equal(grad2, grad)
+    s = prob.stats()
+    assert s.local_noconv == 0 and s.coarse_noconv == 0 and s.nonfinite == 0

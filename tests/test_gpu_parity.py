@@ -125,6 +125,38 @@ def test_small_2d_workload_parity():
     prob.close()
 
 
+@pytest.mark.parametrize("n,r,ns", [((40, 36, 32), (4, 4, 4), 1),     # 10 x 9 x 8 vertices
+                                    ((40, 36, 32), (4, 4, 4), 20),
+                                    ((160, 112), (4, 4), 3),          # 2-D 40 x 28: boxes grow to 8 x 4
+                                    ((64, 64), (3, 4), 4)])           # 2-D, 22 x 16
+def test_coarse_preconditioners_parity(n, r, ns):
+    """Both coarse preconditioners (two-level aggregate correction and plain
+    Jacobi) give D, t and the gradient of the oracle, and agree with each
+    other."""
+    torch = _torch()
+    inst = W.small_instance(n, r, seed=17, ns=ns, nr=9)
+    g = Geometry(n, r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers)
+    V = np.random.default_rng(6).standard_normal(st.D.shape)
+    g_ref = R.jtv(st, V)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    Vd = torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")
+    out = {}
+    for pc in ("twolevel", "jacobi"):
+        prob = _problem(n, r, "reduced", inst, coarse_precond=pc)
+        D = prob.forward(m).cpu().numpy()
+        _, t = prob.coarse()
+        gg = prob.jtv(Vd).cpu().numpy()
+        out[pc] = (D, t, gg, prob.stats().coarse_max_it)
+        assert _rel(D, st.D.T) < 1e-10
+        assert _rel(t, st.t.T) < 1e-10
+        assert _rel(gg, g_ref) < 1e-8
+        prob.close()
+    assert _rel(out["twolevel"][0], out["jacobi"][0]) < 1e-11
+    assert _rel(out["twolevel"][2], out["jacobi"][2]) < 1e-9
+    assert out["twolevel"][3] < out["jacobi"][3]
+
+
 def test_determinism_and_stats():
     torch = _torch()
     n, r = (13, 11, 9), (4, 4, 4)

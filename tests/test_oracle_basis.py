@@ -16,6 +16,8 @@ derivatives (Sec. 4.5).
 * S_k(m + c 1) = S_k(m); Lagrange skeleton values do not depend on m.
 * Tangent against central finite differences; reverse sweep against the
   tangent (dot test).
+* A build restricted to a few entities reproduces the full build's rows of
+  those entities (it is what checks single entities of large grids).
 """
 import numpy as np
 import pytest
@@ -211,3 +213,29 @@ def test_tangent_fd_and_reverse_dot(n, r, mode):
     lhs = basis_vjp(b, V, Z) @ dm
     rhs = np.sum(Z * (dP @ V))
     assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_restricted_build_matches_full(mode):
+    n, r = (17, 13, 11), (4, 4, 3)
+    g = Geometry(n, r)
+    m = np.random.default_rng(8).standard_normal(g.ncell)
+    full = build_basis(g, m, mode)
+    rng = np.random.default_rng(9)
+    picks = []
+    for d in (1, 2, 3):
+        cand = [i for i, e in enumerate(g.entities) if e.dim == d]
+        picks += [cand[0], cand[-1]] + list(rng.choice(cand, 2, replace=False))
+    part = build_basis(g, m, mode, only=picks)
+    for i in picks:
+        cells = g.cell_ids(g.entities[i].cell_ranges)
+        assert np.array_equal(part.cols[cells], full.cols[cells])
+        assert np.array_equal(part.vals[cells], full.vals[cells])
+    # rows outside every picked closure stay empty, vertex rows aside
+    covered = np.zeros(g.ncell, dtype=bool)
+    for i in picks:
+        covered[g.cell_ids(g.entities[i].closure_ranges)] = True
+    for multi in g.vertex_multis():
+        covered[g.vertex_cell(multi)] = True
+    assert (part.cols[~covered] < 0).all()
+    assert (~covered).sum() > g.ncell // 2
