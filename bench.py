@@ -45,6 +45,33 @@ STAGE_WORK = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed_r8.json")
+
+
+def measured_traffic(kernel_stage: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when they were taken on a
+    different kernel source than the one built now."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("stages", {}).get(kernel_stage)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, "paper_1707_07598_amd", "csrc", ent["source"])
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if digest != ent["source_sha256"]:
+        return None
+    return ent["bytes_per_launch"]
+
+
 def cpu_baseline(inst) -> dict:
     """The CPU oracle timed on a bounded sample of the same workload: the
     bottom 128 x 128 x 64 half of the 128^3 field (every electrode and
@@ -82,6 +109,13 @@ def main() -> int:
                     help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-stage events")
+    ap.add_argument("--workload", choices=["c3", "batch"], default="c3",
+                    help="c3: the 128^3 single-instance step (default); batch: 64 mixed "
+                         "instances per call through the batch API")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run 3 device copies of 512 MiB (a kernel of known "
+                         "traffic for scaling the HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -94,6 +128,9 @@ def main() -> int:
 
     import paper_1707_07598_amd as msfv
     import workloads as W
+
+    if args.workload == "batch":
+        return run_batch(args)
 
     inst = W.workload_128()
     dev = torch.device("cuda", 0)
@@ -158,7 +195,7 @@ def main() -> int:
         achieved = flops_per_unit * units_per_launch / avg_s / 1e12
         out["roofline"] = {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom),
             "kernel": dom, "avg_launch_ms": avg_s * 1e3, "units_per_launch": units_per_launch,
             "unit_kind": key, "flops_per_unit": flops_per_unit,
         }
@@ -172,9 +209,97 @@ def main() -> int:
         out["hbm_algorithmic_bytes_per_step"] = hbm_bytes
         out["hbm_frac_of_step"] = hbm_bytes / (ms_per_step / 1e3) / 8e12
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)
     prob.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_batch(args) -> int:
+    """Mixed batch: cubic n ~ U{48..160} (n mod r != 0), r ~ U{4, 8, 16},
+    Ns ~ U{1..32} dipoles, 16 x 16 receivers; one solve = forward + J^T v of
+    one instance.  The plain form runs the instances one after another on
+    one stream; the batch form issues them through msfv_batch_* with the
+    autotuned stream count and graphs."""
+    import numpy as np
+    import torch
+
+    import paper_1707_07598_amd as msfv
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    insts = W.workload_batch(args.batch_count)
+    probs, ms, vs = [], [], []
+    for k, inst in enumerate(insts):
+        p = msfv.Problem(inst.n, inst.r, "reduced")
+        p.set_sources(inst.sources)
+        p.set_receivers(inst.receivers)
+        m = torch.tensor(inst.m, dtype=torch.float64, device=dev)
+        d_obs = p.forward(torch.tensor(inst.m_obs, dtype=torch.float64, device=dev)).clone()
+        v = (p.forward(m) - d_obs).contiguous()
+        probs.append(p)
+        ms.append(m)
+        vs.append(v)
+        print(f"instance {k}: n={inst.n[0]} r={inst.r[0]} ns={inst.sources.count}", file=sys.stderr,
+              flush=True)
+    setup_s = time.perf_counter() - t0
+    cells = sum(int(np.prod(i.n)) for i in insts)
+
+    # plain form: one instance after another on one stream, no graphs
+    for p, m, v in zip(probs, ms, vs):
+        p.forward(m, sync=False)
+        p.jtv(v, sync=False)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, m, v in zip(probs, ms, vs):
+            p.forward(m, sync=False)
+            p.jtv(v, sync=False)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    for p in probs:
+        p.sync()
+
+    b = msfv.Batch(probs)
+    streams, graphs = b.autotune(ms, vs)
+    for _ in range(args.warmup):
+        b.forward_jtv(ms, vs, sync=False)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.forward_jtv(ms, vs, sync=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    b.sync()
+    n = len(probs)
+    value = n * args.steps / elapsed
+    out = {
+        "metric": "MSFV forward+J^T v solves/s, batch of mixed instances (one solve = one instance)",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch-{n}-mixed-n48..160-r4/8/16-ns1..32", "instances": n,
+                   "fine_cells": cells, "sources": int(sum(i.sources.count for i in insts)),
+                   "bc_mode": "reduced"},
+        "plain_solves_per_s": n / plain_s, "speedup_vs_plain": value / (n / plain_s),
+        "autotuned": {"streams": streams, "graphs": graphs}, "setup_s": setup_s,
+    }
+    b.close()
+    for p in probs:
+        p.close()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -91,8 +91,12 @@ typedef struct {
  *                         coarse vertices, M^-1 = D^-1 + Z (Z^T A Z)^-1 Z^T
  *                         (at most 64 boxes); falls back to Jacobi where its
  *                         tables do not fit in on-chip memory.
- *   MSFV_COARSE_JACOBI  : M^-1 = D^-1.                                    */
-enum { MSFV_COARSE_TWOLEVEL = 0, MSFV_COARSE_JACOBI = 1 };
+ *   MSFV_COARSE_JACOBI  : M^-1 = D^-1.
+ *   MSFV_COARSE_MULTI   : M^-1 = D^-1 with the multi-launch solver that
+ *                         grids of more than 16384 vertices always use (all
+ *                         right-hand sides per launch; the call returns when
+ *                         the solve has finished).                         */
+enum { MSFV_COARSE_TWOLEVEL = 0, MSFV_COARSE_JACOBI = 1, MSFV_COARSE_MULTI = 2 };
 
 typedef struct {
   long long ncell;     /* N                                                  */
@@ -118,8 +122,10 @@ typedef struct {
 /* Create a problem for one grid; builds the plan (entity tables, CSR
  * structure of S_k and A_k) and allocates its device state.  hip_stream is a
  * hipStream_t (NULL = default stream).  Unsupported geometry returns
- * MSFV_EINVAL: r outside [3, 16], n < 2 on an axis, or more than 16384
- * coarse vertices. */
+ * MSFV_EINVAL: r outside [3, 16], n < 2 on an axis, more than 2^21 coarse
+ * vertices or 2^31 cells.  Coarse grids of more than 16384 vertices are
+ * solved by a multi-launch Jacobi-PCG whose forward and J^T v calls return
+ * only when their coarse solves have finished (the host polls stop flags). */
 msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem** out);
 
 /* Release all device and host state.  NULL is ignored. */
@@ -185,6 +191,47 @@ typedef struct {
 msfv_status msfv_profile_enable(msfv_problem* p, int enable);
 msfv_status msfv_profile_read(msfv_problem* p, msfv_profile* out);
 const char* msfv_stage_name(int stage);
+
+/* ---- Many problems at once ------------------------------------------------
+ * A batch runs forward (eq. fwdProbRed) followed by J_k^T v (Sec. 4.3) for
+ * each of `count` problems of any shapes, sizes and source counts: the
+ * independent instances of an inversion campaign, as in the paper's
+ * parallel-over-workers setting (Sec. 5, Table 3), here concurrent on one
+ * device.  Problems are issued largest first over a pool of HIP streams so
+ * that small instances fill the compute units left idle by large ones; each
+ * problem's per-call kernel sequence is captured once as a HIP graph per set
+ * of buffer pointers and replayed.  The batch call is asynchronous: it is
+ * ordered after prior work on hip_stream (the batch's stream) and later work
+ * on that stream is ordered after it.  The problems stay owned by the caller
+ * and must outlive the batch; while a batch call is in flight they must not
+ * be used on their own.
+ *
+ * msfv_batch_create : problems[0..count) (not NULL, distinct); hip_stream
+ *                     may be NULL (the null stream).  EINVAL on bad
+ *                     arguments, EDEVICE if streams cannot be created.
+ * msfv_batch_forward_jtv : m[i], v[i] device inputs of problem i (N_i and
+ *                     Nr_i*Ns_i doubles), d_out[i] (Nr_i*Ns_i) and g_out[i]
+ *                     (N_i) device outputs.  Sources and receivers must be
+ *                     set on every problem (ESTATE otherwise).  Outputs are
+ *                     valid after msfv_batch_sync.
+ * msfv_batch_sync   : waits for the batch's work and reports the first
+ *                     failing problem's status (ENOCONV, ENONFINITE).
+ * msfv_batch_set_options / get_options : streams in [1, 16]; graphs 0/1.
+ * msfv_batch_autotune : times one call per candidate (streams 1, 2, 4, 8,
+ *                     16 capped at count; graphs on and off) with the given
+ *                     buffers, keeps the fastest and reports it. */
+typedef struct msfv_batch msfv_batch;
+msfv_status msfv_batch_create(int count, msfv_problem* const* problems, void* hip_stream,
+                              msfv_batch** out);
+void msfv_batch_destroy(msfv_batch* b);
+msfv_status msfv_batch_forward_jtv(msfv_batch* b, const double* const* m, const double* const* v,
+                                   double* const* d_out, double* const* g_out);
+msfv_status msfv_batch_sync(msfv_batch* b);
+msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs);
+msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs);
+msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const double* const* v,
+                                double* const* d_out, double* const* g_out, int* streams_out,
+                                int* graphs_out);
 
 const char* msfv_status_string(msfv_status s);
 const char* msfv_last_error(void);

@@ -25,10 +25,11 @@ from . import _lib
 from ._lib import (MSFV_BC_LAGRANGE, MSFV_BC_REDUCED, MSFV_COARSE_JACOBI,  # noqa: F401
                    MSFV_COARSE_TWOLEVEL, MsfvError)
 
-__all__ = ["Problem", "MSFVForward", "msfv_misfit", "MsfvError"]
+__all__ = ["Problem", "Batch", "MSFVForward", "msfv_misfit", "MsfvError"]
 
 _MODES = {"reduced": MSFV_BC_REDUCED, "lagrange": MSFV_BC_LAGRANGE}
-_COARSE_PRECONDS = {"twolevel": MSFV_COARSE_TWOLEVEL, "jacobi": MSFV_COARSE_JACOBI}
+_COARSE_PRECONDS = {"twolevel": MSFV_COARSE_TWOLEVEL, "jacobi": MSFV_COARSE_JACOBI,
+                    "multi": _lib.MSFV_COARSE_MULTI}
 
 
 def _torch():
@@ -295,3 +296,88 @@ def msfv_misfit(m, problem, d_obs):
     """phi(m) = 1/2 ||F_k(m) - d_obs||_F^2 through the autograd Function."""
     D = _Namespace.MSFVForward.apply(m, problem)
     return 0.5 * ((D - d_obs) ** 2).sum()
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """forward + J^T v of many problems at once (``msfv_batch_*``): problems
+    are issued largest first over a pool of HIP streams, each replaying its
+    captured kernel sequence as a HIP graph.  Outputs D[i] (Ns_i, Nr_i) and
+    g[i] (N_i) are allocated once and reused."""
+
+    def __init__(self, problems: Sequence["Problem"], stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.problems = list(problems)
+        if not self.problems:
+            raise ValueError("empty batch")
+        dev = self.problems[0].device
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        handles = (ctypes.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.msfv_batch_create(len(self.problems), handles,
+                                              ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
+                   "msfv_batch_create")
+        self._h = h
+        self.D = [torch.empty((p._ns, p._nr), dtype=torch.float64, device=dev) for p in self.problems]
+        self.g = [torch.empty(int(np.prod(p.n)), dtype=torch.float64, device=dev) for p in self.problems]
+        self._dp = _ptr_array(self.D)
+        self._gp = _ptr_array(self.g)
+
+    def _check_inputs(self, ms, vs):
+        if len(ms) != len(self.problems) or len(vs) != len(self.problems):
+            raise ValueError("one m and one v per problem")
+        for p, m, v in zip(self.problems, ms, vs):
+            p._check_tensor(m, int(np.prod(p.n)), "m")
+            p._check_tensor(v, p._ns * p._nr, "v")
+
+    def forward_jtv(self, ms, vs, sync: bool = True):
+        """D_i = F(m_i) and g_i = J(m_i)^T v_i for every problem i."""
+        self._check_inputs(ms, vs)
+        self._keep = (ms, vs)
+        _lib.check(self.lib.msfv_batch_forward_jtv(self._h, _ptr_array(ms), _ptr_array(vs),
+                                                   self._dp, self._gp), "msfv_batch_forward_jtv")
+        if sync:
+            self.sync()
+        return self.D, self.g
+
+    def sync(self):
+        _lib.check(self.lib.msfv_batch_sync(self._h), "msfv_batch_sync")
+
+    def set_options(self, streams: int, graphs: bool):
+        _lib.check(self.lib.msfv_batch_set_options(self._h, int(streams), int(bool(graphs))),
+                   "msfv_batch_set_options")
+
+    def options(self):
+        s, g = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.msfv_batch_get_options(self._h, ctypes.byref(s), ctypes.byref(g)),
+                   "msfv_batch_get_options")
+        return s.value, bool(g.value)
+
+    def autotune(self, ms, vs):
+        """Time each candidate (streams x graphs) once and keep the fastest."""
+        self._check_inputs(ms, vs)
+        s, g = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.msfv_batch_autotune(self._h, _ptr_array(ms), _ptr_array(vs), self._dp,
+                                                self._gp, ctypes.byref(s), ctypes.byref(g)),
+                   "msfv_batch_autotune")
+        return s.value, bool(g.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.msfv_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,6 +23,7 @@ MSFV_BC_REDUCED = 0
 MSFV_BC_LAGRANGE = 1
 MSFV_COARSE_TWOLEVEL = 0
 MSFV_COARSE_JACOBI = 1
+MSFV_COARSE_MULTI = 2
 
 STATUS_NAMES = {
     MSFV_OK: "MSFV_OK", MSFV_EINVAL: "MSFV_EINVAL", MSFV_ENOMEM: "MSFV_ENOMEM",
@@ -82,6 +83,15 @@ SIGNATURES = {
     "msfv_profile_enable": (_I, [_P, _I]),
     "msfv_profile_read": (_I, [_P, ctypes.POINTER(MsfvProfile)]),
     "msfv_stage_name": (ctypes.c_char_p, [_I]),
+    "msfv_batch_create": (_I, [_I, ctypes.POINTER(_P), _P, ctypes.POINTER(_P)]),
+    "msfv_batch_destroy": (None, [_P]),
+    "msfv_batch_forward_jtv": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P)]),
+    "msfv_batch_sync": (_I, [_P]),
+    "msfv_batch_set_options": (_I, [_P, _I, _I]),
+    "msfv_batch_get_options": (_I, [_P, _IP, _IP]),
+    "msfv_batch_autotune": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                 ctypes.POINTER(_P), _IP, _IP]),
     "msfv_status_string": (ctypes.c_char_p, [_I]),
     "msfv_last_error": (ctypes.c_char_p, []),
 }

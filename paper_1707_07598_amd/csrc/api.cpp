@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <memory>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -95,6 +97,7 @@ struct msfv_problem {
   Columns src, rec;
   bool electrodes_ready = false;
   bool have_forward = false;
+  unsigned long long generation = 0;  // bumped whenever device buffers are (re)allocated
 
   // plan on the device
   DevBuf<msfv::EntDesc> d_edges, d_faces, d_blocks;
@@ -125,6 +128,12 @@ struct msfv_problem {
   // two-level coarse preconditioner: aggregates and (Z^T A_k Z)^-1
   msfv::CoarseDefl defl;
   DevBuf<double> d_einv;
+  // large coarse systems: solver workspace and pinned stop flags
+  DevBuf<double> d_cg_ws;
+  int* h_flags = nullptr;
+  ~msfv_problem() {
+    if (h_flags) (void)hipHostFree(h_flags);
+  }
   Profiler prof;
 
   size_t workspace_bytes() const {
@@ -133,11 +142,17 @@ struct msfv_problem {
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
-           d_sload.bytes() + d_einv.bytes();
+           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes();
   }
 };
 
 namespace {
+
+// Whether the coarse systems go to the multi-launch solver.
+bool coarse_multi(const msfv_problem* p) {
+  return p->cfg.coarse_precond == MSFV_COARSE_MULTI || msfv::coarse_is_large(p->plan.ncv);
+}
+
 
 // Launch ``expr`` as stage ``id``; with profiling on, bracket it by events.
 #define STAGE(id, expr)                                                              \
@@ -310,8 +325,15 @@ msfv_status build_electrodes(msfv_problem* p) {
   HIP_OK(p->d_lam.alloc(ncs));
   HIP_OK(p->d_D.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
   HIP_OK(p->d_v.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
+  if (coarse_multi(p)) {
+    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, std::max(1, ns)) / sizeof(double) + 1));
+    if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
+    p->h_flags = nullptr;
+    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 3 * std::max(1, ns)));
+  }
   HIP_OK(hipStreamSynchronize(s));  // host vectors above are temporaries
   p->electrodes_ready = true;
+  ++p->generation;
   return MSFV_OK;
 }
 
@@ -344,14 +366,7 @@ msfv::LocalParams base_params(msfv_problem* p) {
 // 1 block adj, 2 face fwd, 3 face adj).
 void set_stats(msfv_problem* p, msfv::LocalParams& lp, int slot) {
   lp.ent_it = p->d_ent_it.ptr + p->ent_off[slot];
-  lp.ent_work = p->d_ent_work.ptr + p->ent_off[slot];
-}
-
-// With profiling on, add the stage's cell-iterations to its work counter.
-hipError_t reduce_stats(msfv_problem* p, int slot, hipStream_t s) {
-  if (!p->prof.on) return hipSuccess;
-  return msfv::launch_reduce_work(p->d_ent_work.ptr + p->ent_off[slot],
-                                  p->ent_off[slot + 1] - p->ent_off[slot], p->d_work.ptr + slot, s);
+  lp.ent_work = p->prof.on ? p->d_ent_work.ptr + p->ent_off[slot] : nullptr;
 }
 
 void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
@@ -367,6 +382,10 @@ void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
 hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned long long* work,
                         hipStream_t s) {
   const msfv::Plan& P = p->plan;
+  if (coarse_multi(p))
+    return msfv::launch_coarse_pcg_large(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
+                                         p->cfg.coarse_maxit, p->d_cg_ws.ptr, p->h_flags,
+                                         p->d_status.ptr, work, s);
   return msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
                                  p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
                                  p->d_status.ptr, work, s);
@@ -385,10 +404,10 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   const msfv::Plan& P = p->plan;
   hipStream_t s = p->stream;
   const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
-  HIP_OK(hipMemsetAsync(p->d_status.ptr, 0, sizeof(int) * msfv::kStCount, s));
-  HIP_OK(hipMemsetAsync(p->d_ent_it.ptr, 0, p->d_ent_it.bytes(), s));
+  HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
+  HIP_OK(msfv::launch_zero(p->d_ent_it.ptr, p->d_ent_it.bytes(), s));
   STAGE(MSFV_STAGE_COPY_M,
-        hipMemcpyAsync(p->d_m.ptr, m, sizeof(double) * P.ncell, hipMemcpyDeviceToDevice, s));
+        msfv::launch_copy(p->d_m.ptr, m, P.ncell, s));
   STAGE(MSFV_STAGE_CHECK, msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
 
   msfv::LocalParams lp = base_params(p);
@@ -403,7 +422,6 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
   set_stats(p, lp, 2);
   STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_local_fwd(lp, 0, s));
-  HIP_OK(reduce_stats(p, 2, s));
 
   if (P.dim == 3) {
     lp = base_params(p);
@@ -412,7 +430,6 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
     set_caps(lp, P.caps_block, P.max_nu_block);
     set_stats(p, lp, 0);
     STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_local_fwd(lp, 0, s));
-    HIP_OK(reduce_stats(p, 0, s));
   }
   STAGE(MSFV_STAGE_KASSEMBLE,
         msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
@@ -423,7 +440,7 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
                                          p->d_status.ptr, s));
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
-  HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
   STAGE(MSFV_STAGE_COARSE_RHS,
         msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
                                   p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
@@ -448,7 +465,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
-  HIP_OK(hipMemsetAsync(p->d_b.ptr, 0, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
   STAGE(MSFV_STAGE_ADJ_RHS,
         msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
                                   p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
@@ -470,7 +487,6 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp.solve_adj = 1;
     set_stats(p, lp, 1);
     STAGE(MSFV_STAGE_BLOCK_ADJ, msfv::launch_local_adj(lp, 0, s));
-    HIP_OK(reduce_stats(p, 1, s));
   }
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
@@ -481,7 +497,6 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
   set_stats(p, lp, 3);
   STAGE(MSFV_STAGE_FACE_ADJ, msfv::launch_local_adj(lp, 0, s));
-  HIP_OK(reduce_stats(p, 3, s));
 
   lp = base_params(p);
   lp.ents = p->d_edges.ptr;
@@ -524,9 +539,10 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   if (p->cfg.local_maxit <= 0) p->cfg.local_maxit = 1000;
   if (p->cfg.coarse_rtol <= 0) p->cfg.coarse_rtol = 1e-13;
   if (p->cfg.coarse_maxit <= 0) p->cfg.coarse_maxit = 20000;
-  if (p->cfg.coarse_precond != MSFV_COARSE_TWOLEVEL && p->cfg.coarse_precond != MSFV_COARSE_JACOBI) {
+  if (p->cfg.coarse_precond != MSFV_COARSE_TWOLEVEL && p->cfg.coarse_precond != MSFV_COARSE_JACOBI &&
+      p->cfg.coarse_precond != MSFV_COARSE_MULTI) {
     delete p;
-    return fail(MSFV_EINVAL, "coarse_precond must be MSFV_COARSE_TWOLEVEL or MSFV_COARSE_JACOBI");
+    return fail(MSFV_EINVAL, "coarse_precond must be MSFV_COARSE_TWOLEVEL, _JACOBI or _MULTI");
   }
   p->stream = static_cast<hipStream_t>(hip_stream);
   std::string err = p->plan.build(cfg->dim, cfg->n, cfg->r);
@@ -535,9 +551,9 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     return fail(MSFV_EINVAL, err);
   }
   const msfv::Plan& P = p->plan;
-  if (P.ncoarse > 16384) {
+  if (P.ncoarse > (1 << 21) || P.ncell >= (int64_t(1) << 31)) {
     delete p;
-    return fail(MSFV_EINVAL, "coarse grid larger than 16384 vertices is not supported");
+    return fail(MSFV_EINVAL, "more than 2^21 coarse vertices or 2^31 cells is not supported");
   }
   for (int k = 0; k < 3; ++k) p->g.n[k] = P.n[k];
   p->g.s1 = P.stride[1];
@@ -575,7 +591,7 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     HIP_OR_CLEAN(p->d_kdia.alloc(size_t(27) * ldk));
   }
   HIP_OR_CLEAN(hipMemsetAsync(p->d_kdia.ptr, 0, p->d_kdia.bytes(), s));
-  if (p->cfg.coarse_precond == MSFV_COARSE_TWOLEVEL) {
+  if (p->cfg.coarse_precond == MSFV_COARSE_TWOLEVEL && !msfv::coarse_is_large(P.ncv)) {
     p->defl = msfv::coarse_defl_plan(P.ncv);
     if (p->defl.ok) {
       HIP_OR_CLEAN(p->d_einv.alloc(size_t(p->defl.na) * p->defl.na));
@@ -670,15 +686,22 @@ msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_o
   return jtv_impl(p, p->d_v.ptr, g_out);
 }
 
-msfv_status msfv_sync(msfv_problem* p) {
-  if (!p) return fail(MSFV_EINVAL, "null problem");
-  HIP_OK(hipStreamSynchronize(p->stream));
+namespace {
+// Status words of the last call (the caller has synchronised).
+msfv_status check_status(msfv_problem* p) {
   int st[msfv::kStCount];
   HIP_OK(hipMemcpy(st, p->d_status.ptr, sizeof st, hipMemcpyDeviceToHost));
   if (st[msfv::kStNonfinite]) return fail(MSFV_ENONFINITE, "m contains NaN or Inf");
   if (st[msfv::kStLocalNoconv] || st[msfv::kStCoarseNoconv])
     return fail(MSFV_ENOCONV, "an iteration reached its cap");
   return MSFV_OK;
+}
+}  // namespace
+
+msfv_status msfv_sync(msfv_problem* p) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  return check_status(p);
 }
 
 msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out) {
@@ -727,6 +750,7 @@ msfv_status msfv_profile_enable(msfv_problem* p, int enable) {
   p->prof.recs.clear();
   p->prof.next = 0;
   HIP_OK(hipMemset(p->d_work.ptr, 0, p->d_work.bytes()));
+  HIP_OK(hipMemset(p->d_ent_work.ptr, 0, p->d_ent_work.bytes()));
   return MSFV_OK;
 }
 
@@ -747,6 +771,16 @@ msfv_status msfv_profile_read(msfv_problem* p, msfv_profile* out) {
   p->prof.next = 0;
   HIP_OK(hipMemcpy(out->work, p->d_work.ptr, sizeof out->work, hipMemcpyDeviceToHost));
   HIP_OK(hipMemset(p->d_work.ptr, 0, p->d_work.bytes()));
+  // local stages: per-entity cell-iterations, summed here in entity order
+  std::vector<unsigned long long> ew(p->d_ent_work.n);
+  if (!ew.empty())
+    HIP_OK(hipMemcpy(ew.data(), p->d_ent_work.ptr, p->d_ent_work.bytes(), hipMemcpyDeviceToHost));
+  for (int slot = 0; slot < 4; ++slot) {
+    unsigned long long t = 0;
+    for (int e = p->ent_off[slot]; e < p->ent_off[slot + 1]; ++e) t += ew[e];
+    out->work[slot] = t;
+  }
+  HIP_OK(hipMemset(p->d_ent_work.ptr, 0, p->d_ent_work.bytes()));
   return MSFV_OK;
 }
 
@@ -774,6 +808,216 @@ msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out) {
   out->coarse_max_it = st[msfv::kStCoarseMaxIt];
   out->coarse_noconv = st[msfv::kStCoarseNoconv];
   out->nonfinite = st[msfv::kStNonfinite];
+  return MSFV_OK;
+}
+
+
+// ---- batches ----------------------------------------------------------------
+
+struct msfv_batch {
+  std::vector<msfv_problem*> probs;
+  std::vector<int> order;        // issue order: most fine cells first
+  hipStream_t main = nullptr;    // caller's stream
+  std::vector<hipStream_t> pool; // owned, default priority
+  std::vector<hipEvent_t> done;  // one per pool stream
+  hipEvent_t fork = nullptr;
+  int streams = 8;
+  bool graphs = true;
+  struct Graph {
+    const double* m = nullptr;
+    const double* v = nullptr;
+    double* d = nullptr;
+    double* g = nullptr;
+    unsigned long long generation = ~0ull;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> cache;      // one per problem
+  ~msfv_batch() {
+    if (main) (void)hipStreamSynchronize(main);
+    for (auto s : pool) (void)hipStreamSynchronize(s);
+    for (auto& c : cache)
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    for (auto e : done) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto s : pool) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace {
+
+// forward + J^T v of one problem on stream s (eager or through its graph)
+msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, double* d, double* g,
+                      hipStream_t s) {
+  msfv_problem* p = b->probs[i];
+  const hipStream_t own = p->stream;
+  const bool prof = p->prof.on;
+  p->stream = s;
+  p->prof.on = false;
+  msfv_status st = MSFV_OK;
+  // the large coarse solver polls from the host, which a graph cannot hold
+  if (!b->graphs || coarse_multi(p)) {
+    st = forward_impl(p, m, d, nullptr);
+    if (st == MSFV_OK) st = jtv_impl(p, v, g);
+  } else {
+    msfv_batch::Graph& c = b->cache[i];
+    if (!c.exec || c.m != m || c.v != v || c.d != d || c.g != g || c.generation != p->generation) {
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+      c.exec = nullptr;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        st = forward_impl(p, m, d, nullptr);
+        if (st == MSFV_OK) st = jtv_impl(p, v, g);
+        e = hipStreamEndCapture(s, &graph);
+        if (st == MSFV_OK && e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (st == MSFV_OK && e != hipSuccess) st = fail(MSFV_EDEVICE, hipGetErrorString(e));
+      if (st == MSFV_OK) {
+        c.m = m;
+        c.v = v;
+        c.d = d;
+        c.g = g;
+        c.generation = p->generation;
+      }
+    }
+    if (st == MSFV_OK) {
+      hipError_t e = hipGraphLaunch(c.exec, s);
+      if (e != hipSuccess) st = fail(MSFV_EDEVICE, hipGetErrorString(e));
+    }
+  }
+  p->stream = own;
+  p->prof.on = prof;
+  return st;
+}
+
+msfv_status batch_run(msfv_batch* b, const double* const* m, const double* const* v,
+                      double* const* d_out, double* const* g_out) {
+  const int n = int(b->probs.size());
+  for (int i = 0; i < n; ++i) {
+    if (!m[i] || !v[i] || !d_out[i] || !g_out[i]) return fail(MSFV_EINVAL, "null buffer in batch");
+    msfv_status st = ensure_ready(b->probs[i]);
+    if (st != MSFV_OK) return st;
+  }
+  const int ns = std::min<int>(b->streams, int(b->pool.size()));
+  HIP_OK(hipEventRecord(b->fork, b->main));
+  for (int k = 0; k < ns; ++k) HIP_OK(hipStreamWaitEvent(b->pool[k], b->fork, 0));
+  for (int q = 0; q < n; ++q) {
+    const int i = b->order[q];
+    msfv_status st = batch_one(b, i, m[i], v[i], d_out[i], g_out[i], b->pool[q % ns]);
+    if (st != MSFV_OK) return st;
+  }
+  for (int k = 0; k < ns; ++k) {
+    HIP_OK(hipEventRecord(b->done[k], b->pool[k]));
+    HIP_OK(hipStreamWaitEvent(b->main, b->done[k], 0));
+  }
+  return MSFV_OK;
+}
+
+}  // namespace
+
+msfv_status msfv_batch_create(int count, msfv_problem* const* problems, void* hip_stream,
+                              msfv_batch** out) {
+  if (!out || !problems || count <= 0) return fail(MSFV_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  std::unique_ptr<msfv_batch> b(new msfv_batch());
+  for (int i = 0; i < count; ++i) {
+    if (!problems[i]) return fail(MSFV_EINVAL, "null problem in batch");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return fail(MSFV_EINVAL, "a problem appears twice in the batch");
+    b->probs.push_back(problems[i]);
+  }
+  b->order.resize(count);
+  for (int i = 0; i < count; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+    return b->probs[x]->plan.ncell > b->probs[y]->plan.ncell;
+  });
+  b->cache.resize(count);
+  b->main = static_cast<hipStream_t>(hip_stream);
+  constexpr int kPool = 16;
+  for (int k = 0; k < kPool; ++k) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+      return fail(MSFV_EDEVICE, "hipStreamCreate failed");
+    b->pool.push_back(s);
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(MSFV_EDEVICE, "hipEventCreate failed");
+    b->done.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+    return fail(MSFV_EDEVICE, "hipEventCreate failed");
+  b->streams = std::min(8, count);
+  *out = b.release();
+  return MSFV_OK;
+}
+
+void msfv_batch_destroy(msfv_batch* b) { delete b; }
+
+msfv_status msfv_batch_forward_jtv(msfv_batch* b, const double* const* m, const double* const* v,
+                                   double* const* d_out, double* const* g_out) {
+  if (!b || !m || !v || !d_out || !g_out) return fail(MSFV_EINVAL, "null argument");
+  return batch_run(b, m, v, d_out, g_out);
+}
+
+msfv_status msfv_batch_sync(msfv_batch* b) {
+  if (!b) return fail(MSFV_EINVAL, "null batch");
+  HIP_OK(hipStreamSynchronize(b->main));
+  for (auto s : b->pool) HIP_OK(hipStreamSynchronize(s));
+  for (msfv_problem* p : b->probs) {
+    msfv_status st = check_status(p);
+    if (st != MSFV_OK) return st;
+  }
+  return MSFV_OK;
+}
+
+msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs) {
+  if (!b) return fail(MSFV_EINVAL, "null batch");
+  if (streams < 1 || streams > int(b->pool.size())) return fail(MSFV_EINVAL, "streams outside [1, 16]");
+  b->streams = streams;
+  b->graphs = graphs != 0;
+  return MSFV_OK;
+}
+
+msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs) {
+  if (!b) return fail(MSFV_EINVAL, "null batch");
+  if (streams) *streams = b->streams;
+  if (graphs) *graphs = b->graphs ? 1 : 0;
+  return MSFV_OK;
+}
+
+msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const double* const* v,
+                                double* const* d_out, double* const* g_out, int* streams_out,
+                                int* graphs_out) {
+  if (!b || !m || !v || !d_out || !g_out) return fail(MSFV_EINVAL, "null argument");
+  const int count = int(b->probs.size());
+  double best = 1e300;
+  int best_s = b->streams;
+  bool best_g = b->graphs;
+  for (int gr = 1; gr >= 0; --gr) {
+    for (int sc : {1, 2, 4, 8, 16}) {
+      if (sc > count && sc != 1) continue;
+      b->streams = sc;
+      b->graphs = gr != 0;
+      msfv_status st = batch_run(b, m, v, d_out, g_out);  // warm: captures graphs
+      if (st == MSFV_OK) st = msfv_batch_sync(b);
+      if (st != MSFV_OK) return st;
+      const auto t0 = std::chrono::steady_clock::now();
+      st = batch_run(b, m, v, d_out, g_out);
+      if (st == MSFV_OK) st = msfv_batch_sync(b);
+      if (st != MSFV_OK) return st;
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (dt < best) {
+        best = dt;
+        best_s = sc;
+        best_g = gr != 0;
+      }
+    }
+  }
+  b->streams = best_s;
+  b->graphs = best_g;
+  if (streams_out) *streams_out = best_s;
+  if (graphs_out) *graphs_out = best_g ? 1 : 0;
   return MSFV_OK;
 }
 

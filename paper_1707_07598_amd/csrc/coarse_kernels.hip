@@ -361,6 +361,188 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Large coarse systems (more rows than one workgroup can stage in LDS):
+// Jacobi-PCG for all right-hand sides together, one launch per phase:
+//   spmv_dot : q_j = A p_j and per-tile partials of p_j.q_j (the coefficients
+//              of a tile of rows are loaded once for a group of 8 sources);
+//   update   : alpha_j from the partials, x_j += alpha p_j, r_j -= alpha q_j,
+//              partials of r_j.z_j and r_j.r_j (z = D^-1 r);
+//   pupdate  : beta_j and the stop test from the partials, p_j = z_j + beta p_j.
+// Every workgroup sums the per-tile partials itself, in tile order, so all
+// agree bit for bit without a separate scalar launch.  Per-source scalars
+// that a phase both reads and writes are double-buffered by iteration parity.
+constexpr int kMT = 256;  // rows per tile (one per thread)
+constexpr int kMG = 8;    // sources per spmv workgroup
+
+struct CgmState {
+  double* r;      // ns * nc
+  double* p;      // ns * nc
+  double* q;      // ns * nc
+  double* part;   // 3 * ns * ntile: p.q, r.z, r.r
+  double* scal;   // per source: rz[2], bb
+  int* flag;      // per source: done[2], unused
+};
+
+template <int NW>
+__device__ __forceinline__ double tile_sum(double v, double* red) {
+  v = wsum(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < NW; ++w) t += red[w];
+  return t;
+}
+
+__device__ __forceinline__ double sum_parts(const double* part, int ntile) {
+  double t = 0.0;
+  for (int b = 0; b < ntile; ++b) t += part[b];
+  return t;
+}
+
+__global__ __launch_bounds__(kMT) void k_cgm_init(const double* __restrict__ kdia, int ldk, int nc,
+                                                  int ns, int ntile, const double* __restrict__ rhs,
+                                                  double* __restrict__ x, CgmState S) {
+  __shared__ double red[kMT / kWave];
+  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  const bool live = i < nc && i != 0;
+  const double dg = live ? kdia[13 * size_t(ldk) + i] : 0.0;
+  const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
+  const size_t o = size_t(j) * nc + i;
+  const double r = live ? rhs[o] : 0.0;
+  const double z = r * dinv;
+  if (i < nc) {
+    x[o] = 0.0;
+    S.r[o] = r;
+    S.p[o] = z;
+  }
+  const double rz = tile_sum<kMT / kWave>(r * z, red);
+  const double rr = tile_sum<kMT / kWave>(r * r, red);
+  if (threadIdx.x == 0) {
+    S.part[(size_t(1) * ns + j) * ntile + blockIdx.x] = rz;
+    S.part[(size_t(2) * ns + j) * ntile + blockIdx.x] = rr;
+  }
+}
+
+// scalars of the initial residual (one thread per source)
+__global__ void k_cgm_start(int ns, int ntile, CgmState S) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile);
+  const double bb = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile);
+  S.scal[3 * j + 0] = rz;
+  S.scal[3 * j + 1] = rz;
+  S.scal[3 * j + 2] = bb;
+  const int done = bb > 0.0 ? 0 : 1;
+  S.flag[3 * j + 0] = done;
+  S.flag[3 * j + 1] = done;
+  S.flag[3 * j + 2] = 0;
+}
+
+__global__ __launch_bounds__(kMT) void k_cgm_spmv(const double* __restrict__ kdia, int ldk, int ncx,
+                                                  int ncy, int ncz, int ns, int ntile, int par,
+                                                  CgmState S) {
+  __shared__ double red[kMT / kWave];
+  const int nc = ncx * ncy * ncz;
+  const int i = blockIdx.x * kMT + threadIdx.x;
+  const int j0 = blockIdx.y * kMG;
+  const bool live = i < nc && i != 0;
+  const int x = i % ncx, y = (i / ncx) % ncy, z = i / (ncx * ncy);
+  double k[27];
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+    const bool in = live && x + dx >= 0 && x + dx < ncx && y + dy >= 0 && y + dy < ncy &&
+                    z + dz >= 0 && z + dz < ncz && i + dx + ncx * (dy + ncy * dz) != 0;
+    k[o] = in ? kdia[size_t(o) * ldk + i] : 0.0;
+  }
+  for (int jj = 0; jj < kMG; ++jj) {
+    const int j = j0 + jj;
+    if (j >= ns) break;
+    if (S.flag[3 * j + par]) continue;  // uniform over the workgroup
+    const double* pj = S.p + size_t(j) * nc;
+    double q = 0.0;
+    if (live) {
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        const int off = (o % 3 - 1) + ncx * ((o / 3) % 3 - 1 + ncy * (o / 9 - 1));
+        if (k[o] != 0.0) q += k[o] * pj[i + off];
+      }
+      S.q[size_t(j) * nc + i] = q;
+    }
+    const double pq = tile_sum<kMT / kWave>(live ? pj[i] * q : 0.0, red);
+    if (threadIdx.x == 0) S.part[(size_t(0) * ns + j) * ntile + blockIdx.x] = pq;
+  }
+}
+
+__global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ kdia, int ldk, int nc,
+                                                    int ns, int ntile, int par,
+                                                    double* __restrict__ x, CgmState S) {
+  __shared__ double red[kMT / kWave];
+  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  if (S.flag[3 * j + par]) return;  // uniform over the workgroup
+  const double pq = sum_parts(S.part + (size_t(0) * ns + j) * ntile, ntile);
+  const double alpha = pq != 0.0 ? S.scal[3 * j + par] / pq : 0.0;
+  const bool live = i < nc && i != 0;
+  double rz = 0.0, rr = 0.0;
+  if (live) {
+    const size_t o = size_t(j) * nc + i;
+    const double dg = kdia[13 * size_t(ldk) + i];
+    const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
+    x[o] += alpha * S.p[o];
+    const double r = S.r[o] - alpha * S.q[o];
+    S.r[o] = r;
+    rz = r * r * dinv;
+    rr = r * r;
+  }
+  rz = tile_sum<kMT / kWave>(rz, red);
+  rr = tile_sum<kMT / kWave>(rr, red);
+  if (threadIdx.x == 0) {
+    S.part[(size_t(1) * ns + j) * ntile + blockIdx.x] = rz;
+    S.part[(size_t(2) * ns + j) * ntile + blockIdx.x] = rr;
+  }
+}
+
+// it: number of this iteration (1-based, the same for every source)
+__global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ kdia, int ldk, int nc,
+                                                     int ns, int ntile, int par, int it, double tol2,
+                                                     int maxit, CgmState S, int* status,
+                                                     unsigned long long* work) {
+  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  const int nxt = par ^ 1;
+  if (S.flag[3 * j + par]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S.flag[3 * j + nxt] = 1;
+      S.scal[3 * j + nxt] = S.scal[3 * j + par];
+    }
+    return;
+  }
+  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile);
+  const double rr = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile);
+  const bool conv = rr <= tol2 * S.scal[3 * j + 2];
+  const bool bad = rr != rr || (!conv && it >= maxit);
+  const bool stop = conv || bad;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.flag[3 * j + nxt] = stop ? 1 : 0;
+    S.scal[3 * j + nxt] = rz;
+    if (stop) {
+      atomicMax(status + kStCoarseMaxIt, it);
+      if (bad) atomicAdd(status + kStCoarseNoconv, 1);
+      if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
+    }
+  }
+  if (stop || i >= nc || i == 0) return;
+  const double rzo = S.scal[3 * j + par];
+  const double beta = rzo != 0.0 ? rz / rzo : 0.0;
+  const size_t o = size_t(j) * nc + i;
+  const double dg = kdia[13 * size_t(ldk) + i];
+  const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
+  S.p[o] = S.r[o] * dinv + beta * S.p[o];
+}
+
 constexpr int kBlock = 1024;
 
 size_t pcg_lds_bytes(int ldk, int pad, int na) {
@@ -373,8 +555,68 @@ size_t setup_lds_bytes(int na) { return size_t(na) * na * sizeof(double); }
 
 int coarse_ldk(int nc) {
   const int rpt = (nc + kBlock - 1) / kBlock;
+  if (rpt > 16) return rpt * kBlock;  // large systems: no LDS staging, rows just padded
   const int r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : 16;
   return r * kBlock;
+}
+
+bool coarse_is_large(const int ncv[3]) {
+  const int nc = ncv[0] * ncv[1] * ncv[2];
+  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  return nc > 16 * kBlock || pcg_lds_bytes(coarse_ldk(nc), pad, 0) > 160 * 1024;
+}
+
+size_t coarse_large_workspace(const int ncv[3], int ns) {
+  const size_t nc = size_t(ncv[0]) * ncv[1] * ncv[2];
+  const size_t ntile = (nc + kMT - 1) / kMT;
+  return (3 * nc * ns + 3 * ntile * ns + 3 * size_t(ns)) * sizeof(double) + 3 * size_t(ns) * sizeof(int);
+}
+
+hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const double* rhs, double* x,
+                                   int ns, double rtol, int maxit, void* workspace, int* host_flags,
+                                   int* status, unsigned long long* work, hipStream_t s) {
+  if (ns == 0) return hipSuccess;
+  const int nc = ncv[0] * ncv[1] * ncv[2];
+  const int ldk = coarse_ldk(nc);
+  const int ntile = (nc + kMT - 1) / kMT;
+  CgmState S;
+  double* w = static_cast<double*>(workspace);
+  S.r = w;
+  S.p = S.r + size_t(ns) * nc;
+  S.q = S.p + size_t(ns) * nc;
+  S.part = S.q + size_t(ns) * nc;
+  S.scal = S.part + size_t(3) * ntile * ns;
+  S.flag = reinterpret_cast<int*>(S.scal + size_t(3) * ns);
+  const dim3 gt(ntile, ns), gs(ntile, (ns + kMG - 1) / kMG);
+  hipLaunchKernelGGL(k_cgm_init, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, rhs, x, S);
+  hipLaunchKernelGGL(k_cgm_start, dim3((ns + 255) / 256), dim3(256), 0, s, ns, ntile, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double tol2 = rtol * rtol;
+  // Phases are issued in chunks; between chunks the host reads the stop
+  // flags (a few bytes) and ends the loop when every source has stopped.
+  constexpr int kChunk = 8;
+  int it = 0, par = 0;
+  while (it < maxit) {
+    for (int c = 0; c < kChunk && it < maxit; ++c, ++it) {
+      hipLaunchKernelGGL(k_cgm_spmv, gs, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], ncv[2], ns, ntile,
+                         par, S);
+      hipLaunchKernelGGL(k_cgm_update, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, par, x, S);
+      hipLaunchKernelGGL(k_cgm_pupdate, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, par, it + 1,
+                         tol2, maxit, S, status, work);
+      par ^= 1;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_flags, S.flag, sizeof(int) * 3 * ns, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    bool all = true;
+    for (int j = 0; j < ns; ++j) all = all && host_flags[3 * j + par] != 0;
+    if (all) break;
+  }
+  return hipSuccess;
 }
 
 CoarseDefl coarse_defl_plan(const int ncv[3]) {

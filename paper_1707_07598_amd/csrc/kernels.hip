@@ -368,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
     if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
     if (a.ent_it) {
       a.ent_it[blockIdx.x] = itmax;
-      a.ent_work[blockIdx.x] = work;
+      if (a.ent_work) a.ent_work[blockIdx.x] += work;
     }
   }
   __syncthreads();  // S_k rows of this entity are visible to the workgroup
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
       if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
       if (a.ent_it) {
         a.ent_it[blockIdx.x] = itmax;
-        a.ent_work[blockIdx.x] = work;
+        if (a.ent_work) a.ent_work[blockIdx.x] += work;
       }
     }
   }
@@ -805,17 +805,14 @@ __global__ void k_check_finite(const double* m, long long n, int* status) {
   if (bad) atomicOr(status + kStNonfinite, 1);
 }
 
-__global__ void k_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work) {
-  __shared__ unsigned long long part[256];
-  unsigned long long acc = 0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += ent_work[i];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) work[0] += part[0];
+__global__ void k_zero_words(unsigned* p, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_copy_d(double* __restrict__ dst, const double* __restrict__ src, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 __global__ void k_set_ones(const int* idx, int n, double* out) {
@@ -1006,10 +1003,17 @@ hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s) {
 hipError_t launch_local_fwd(const LocalParams& p, int, hipStream_t s) { return launch_local(p, false, s); }
 hipError_t launch_local_adj(const LocalParams& p, int, hipStream_t s) { return launch_local(p, true, s); }
 
-hipError_t launch_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work,
-                              hipStream_t s) {
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 4);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_work, dim3(1), dim3(256), 0, s, ent_work, n, work);
+  hipLaunchKernelGGL(k_zero_words, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<unsigned*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_d, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

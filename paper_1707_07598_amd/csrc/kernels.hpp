@@ -60,7 +60,7 @@ struct LocalParams {
   int solve_adj = 1;               // 0: flux-derivative (G) term only
   int push = 1;                    // 1: push loads to lower entities
   int* ent_it = nullptr;                  // per entity: largest CG iteration count of its corners
-  unsigned long long* ent_work = nullptr; // per entity: CG cell-iterations (iterations x own cells)
+  unsigned long long* ent_work = nullptr; // per entity, if set: += CG cell-iterations (iterations x own cells)
 };
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
@@ -68,9 +68,10 @@ hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s);
 hipError_t launch_local_fwd(const LocalParams& p, int kind_rmax, hipStream_t s);
 hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s);
 hipError_t launch_local_adj(const LocalParams& p, int kind_rmax, hipStream_t s);
-// work[0] += sum of ent_work[0..n) (one workgroup, fixed summation order)
-hipError_t launch_reduce_work(const unsigned long long* ent_work, int n, unsigned long long* work,
-                              hipStream_t s);
+// Zero `bytes` (a multiple of 4) / copy n doubles with plain kernels, so that
+// the per-call sequence holds only kernel launches (safe to capture in a graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s);
 hipError_t launch_set_ones(const int* idx, int n, double* out, hipStream_t s);
 // A_k as CSR (kval) and as 27 diagonals of the coarse grid (kdia[o*ldk + row],
 // o = (dx+1) + 3(dy+1) + 9(dz+1), ldk = coarse_ldk(nc)); dslot maps each CSR
@@ -94,6 +95,16 @@ CoarseDefl coarse_defl_plan(const int ncv[3]);
 // non-converged coarse solve in status.
 hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
                                     double* einv, int* status, hipStream_t s);
+// Coarse systems too large for one workgroup's LDS take the multi-launch
+// solver: Jacobi-PCG over all columns, three launches per iteration, and the
+// host polls the stop flags every few iterations (so the call blocks until
+// the solve ends).  workspace: coarse_large_workspace bytes of device memory;
+// host_flags: 3*ns ints of pinned host memory.
+bool coarse_is_large(const int ncv[3]);
+size_t coarse_large_workspace(const int ncv[3], int ns);
+hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const double* rhs, double* x,
+                                   int ns, double rtol, int maxit, void* workspace, int* host_flags,
+                                   int* status, unsigned long long* work, hipStream_t s);
 // PCG on A_k with vertex 0 fixed, one workgroup per column of rhs; Jacobi
 // preconditioned, plus the aggregate correction when defl is given.
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
         wk += (unsigned long long)S.wit[q] * E.nu;
       }
     a.ent_it[blockIdx.x] = itm;
-    a.ent_work[blockIdx.x] = wk;
+    if (a.ent_work) a.ent_work[blockIdx.x] += wk;
   }
   // energy block K_E = sum over the touched fluxes T dphi dphi^T: one thread
   // per own cell and its owned fluxes, then a fixed-order block reduction
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
         wk += (unsigned long long)S.wit[q] * E.nu;
       }
     a.ent_it[blockIdx.x] = itm;
-    a.ent_work[blockIdx.x] = wk;
+    if (a.ent_work) a.ent_work[blockIdx.x] += wk;
   }
   // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for owned fluxes
   const int ncol = w.Ua * w.Ub;

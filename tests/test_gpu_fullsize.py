@@ -2,6 +2,9 @@
 
 * 64^3, r = 8, 16 surface dipoles, 256 receivers: D, t and the gradient
   element-wise against the oracle (same bars as the small cases).
+* a grid of more than 16384 coarse vertices (132 x 132 x 68, r = 4: 33 x 33
+  x 17), which takes the multi-launch coarse solver: pinned coarse residual,
+  Galerkin invariants and a finite-difference directional derivative.
 * 128^3, r = 8, 32 surface dipoles, 1024 receivers, in the launch
   configuration the benchmark times (automatic coarse mode, every stage on
   the device): sampled basis rows and coarse-operator rows against the
@@ -159,3 +162,37 @@ def test_128_gradient_fd_and_determinism(full128):
     assert torch.equal(grad2, grad)
     s = prob.stats()
     assert s.local_noconv == 0 and s.coarse_noconv == 0 and s.nonfinite == 0
+
+
+def test_large_coarse_grid_properties():
+    import torch
+    n, r = (132, 132, 68), (4, 4, 4)
+    inst = W.small_instance(n, r, seed=19, ns=5, nr=49, corr=6.0)
+    prob = _problem(inst)
+    sz = prob.sizes()
+    assert sz.ncoarse == 33 * 33 * 17
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    d_obs = prob.forward(torch.tensor(inst.m_obs, dtype=torch.float64, device="cuda")).clone()
+    phi, grad = prob.misfit_grad(m, d_obs)
+    rp, col, val = prob.prolongation()
+    P = sp.csr_matrix((val, col, rp), shape=(sz.ncell, sz.ncoarse))
+    (krp, kcol, kval), t = prob.coarse()
+    K = sp.csr_matrix((kval, kcol, krp), shape=(sz.ncoarse,) * 2)
+    Q = R.columns_matrix(sz.ncell, inst.sources)
+    B = np.asarray((P.T @ Q).todense())
+    res = K[1:, 1:] @ t[:, 1:].T - B[1:]
+    assert np.all(t[:, 0] == 0.0)
+    assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(B[1:])
+    d = K.diagonal()
+    assert abs(K - K.T).max() <= 1e-12 * d.max()
+    assert np.abs(np.asarray(K.sum(axis=1)).ravel()).max() <= 1e-11 * d.max()
+    e = torch.tensor(np.random.default_rng(24).standard_normal(m.numel()), device="cuda")
+    h = 1e-5
+    fp, _ = prob.misfit_grad(m + h * e, d_obs)
+    fm, _ = prob.misfit_grad(m - h * e, d_obs)
+    fd = (fp.item() - fm.item()) / (2 * h)
+    dd = (grad * e).sum().item()
+    assert abs(fd - dd) <= 1e-5 * abs(dd)
+    s = prob.stats()
+    assert s.coarse_noconv == 0 and s.local_noconv == 0
+    prob.close()

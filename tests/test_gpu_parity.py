@@ -130,9 +130,9 @@ def test_small_2d_workload_parity():
                                     ((160, 112), (4, 4), 3),          # 2-D 40 x 28: boxes grow to 8 x 4
                                     ((64, 64), (3, 4), 4)])           # 2-D, 22 x 16
 def test_coarse_preconditioners_parity(n, r, ns):
-    """Both coarse preconditioners (two-level aggregate correction and plain
-    Jacobi) give D, t and the gradient of the oracle, and agree with each
-    other."""
+    """The coarse solvers (two-level aggregate correction, plain Jacobi, and
+    the multi-launch Jacobi solver of large grids) give D, t and the gradient
+    of the oracle, and agree with each other."""
     torch = _torch()
     inst = W.small_instance(n, r, seed=17, ns=ns, nr=9)
     g = Geometry(n, r)
@@ -142,7 +142,7 @@ def test_coarse_preconditioners_parity(n, r, ns):
     m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
     Vd = torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")
     out = {}
-    for pc in ("twolevel", "jacobi"):
+    for pc in ("twolevel", "jacobi", "multi"):
         prob = _problem(n, r, "reduced", inst, coarse_precond=pc)
         D = prob.forward(m).cpu().numpy()
         _, t = prob.coarse()
@@ -152,8 +152,9 @@ def test_coarse_preconditioners_parity(n, r, ns):
         assert _rel(t, st.t.T) < 1e-10
         assert _rel(gg, g_ref) < 1e-8
         prob.close()
-    assert _rel(out["twolevel"][0], out["jacobi"][0]) < 1e-11
-    assert _rel(out["twolevel"][2], out["jacobi"][2]) < 1e-9
+    for pc in ("jacobi", "multi"):
+        assert _rel(out["twolevel"][0], out[pc][0]) < 1e-11
+        assert _rel(out["twolevel"][2], out[pc][2]) < 1e-9
     assert out["twolevel"][3] < out["jacobi"][3]
 
 
