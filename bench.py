@@ -109,9 +109,14 @@ def main() -> int:
                     help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-stage events")
-    ap.add_argument("--workload", choices=["c3", "batch"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "batch", "serve"], default="c3",
                     help="c3: the 128^3 single-instance step (default); batch: 64 mixed "
-                         "instances per call through the batch API")
+                         "instances per call through the batch API; serve: 16 jobs, Poisson "
+                         "arrivals at 0.5x, 1x and 2x the measured capacity")
+    ap.add_argument("--serve-jobs", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests per load point")
+    ap.add_argument("--serve-inflight", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run 3 device copies of 512 MiB (a kernel of known "
@@ -131,6 +136,17 @@ def main() -> int:
 
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "serve":
+        sv = run_serve(args.serve_jobs, args.serve_requests, args.serve_inflight)
+        one = sv["load_points"]["1.0"]
+        out = {"metric": "MSFV serve p99 latency at 1x measured capacity (forward + J^T v requests)",
+               "value": one["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.serve_requests,
+               "warmup": args.serve_jobs, "ms_per_step": one["mean_ms"], "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"serve-{sv['jobs']}-jobs-n32..192-r8-ns1..64-poisson"},
+               "serve": sv}
+        print(json.dumps(out), flush=True)
+        return 0
 
     inst = W.workload_128()
     dev = torch.device("cuda", 0)
@@ -222,6 +238,92 @@ def main() -> int:
     prob.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def run_serve(jobs: int, nreq: int, inflight: int, log=sys.stderr) -> dict:
+    """Serving: inversion jobs with n ~ U{32..192}, r = 8, 16 x 16 receivers;
+    request i of a job is forward + J^T v at model m_i (m_0, or m_0 plus a 1 %
+    GRF step, alternating) with Ns ~ U{1..64} dipoles.  Capacity is the
+    closed-loop rate of nreq requests submitted at once; then Poisson arrivals
+    at 0.5x, 1x and 2x that rate, nreq requests each, latency from
+    submission to completion."""
+    import numpy as np
+    import torch
+
+    import paper_1707_07598_amd as msfv
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    js = W.workload_serving(jobs)
+    srv = msfv.Server(max_inflight=inflight)
+    state = []
+    rng = np.random.default_rng(W.config_seed(5, 999))
+    for k, job in enumerate(js):
+        p = msfv.Problem(job.n, job.r, "reduced", stream=torch.cuda.Stream(dev))
+        p.set_receivers(job.receivers)
+        srv.add_job(p)
+        m0 = torch.tensor(job.m0, dtype=torch.float64, device=dev)
+        m1 = torch.tensor(job.model(1), dtype=torch.float64, device=dev)
+        nr = job.receivers.count
+        v = torch.tensor(rng.standard_normal((64, nr)), dtype=torch.float64, device=dev)
+        d = torch.empty((64, nr), dtype=torch.float64, device=dev)
+        g = torch.empty(int(np.prod(job.n)), dtype=torch.float64, device=dev)
+        state.append({"p": p, "m": (m0, m1), "v": v, "d": d, "g": g, "it": 0, "job": job})
+        print(f"job {k}: n={job.n[0]}", file=log, flush=True)
+    setup_s = time.perf_counter() - t0
+
+    def submit_one():
+        k = int(rng.integers(0, len(state)))
+        s = state[k]
+        i = s["it"]
+        s["it"] += 1
+        src = s["job"].sources(i)
+        ns = src.count
+        return srv.submit(k, src, s["m"][i % 2], s["v"][:ns], s["d"][:ns], s["g"])
+
+    # warm-up: every job once (builds electrode tables, first-touch allocations)
+    for k in range(len(state)):
+        s = state[k]
+        src = s["job"].sources(0)
+        srv.wait(srv.submit(k, src, s["m"][0], s["v"][:src.count], s["d"][:src.count], s["g"]))
+    srv.stats(reset=True)
+    # capacity: closed loop
+    t1 = time.perf_counter()
+    ids = [submit_one() for _ in range(nreq)]
+    for rid in ids:
+        srv.wait(rid)
+    cap = nreq / (time.perf_counter() - t1)
+    closed = srv.stats(reset=True)
+    points = {}
+    for f in (0.5, 1.0, 2.0):
+        lam = f * cap
+        gaps = rng.exponential(1.0 / lam, nreq)
+        ids = []
+        t_next = time.perf_counter()
+        for gap in gaps:
+            t_next += gap
+            while True:
+                dt = t_next - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.002))
+            ids.append(submit_one())
+        for rid in ids:
+            srv.wait(rid)
+        st = srv.stats(reset=True)
+        points[str(f)] = {"offered_per_s": lam, "served_per_s": st["throughput"],
+                          "p50_ms": st["p50_ms"], "p90_ms": st["p90_ms"], "p99_ms": st["p99_ms"],
+                          "mean_ms": st["mean_ms"], "failed": st["failed"]}
+        print(f"load {f}: {points[str(f)]}", file=log, flush=True)
+    srv.close()
+    for s in state:
+        s["p"].close()
+    return {"jobs": len(js), "requests_per_point": nreq, "max_inflight": inflight,
+            "capacity_per_s": cap, "closed_loop_p50_ms": closed["p50_ms"],
+            "closed_loop_p99_ms": closed["p99_ms"], "load_points": points, "setup_s": setup_s,
+            "job_sizes": [j.n[0] for j in js]}
 
 
 def run_batch(args) -> int:

@@ -233,6 +233,49 @@ msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const dou
                                 double* const* d_out, double* const* g_out, int* streams_out,
                                 int* graphs_out);
 
+/* ---- Serving ----------------------------------------------------------------
+ * A server runs forward (eq. fwdProbRed) + J_k^T v (Sec. 4.3) requests for
+ * registered jobs -- the per-iteration evaluations of many concurrent
+ * inversions (Sec. 2.2) -- as they arrive.  A dispatcher thread owned by the
+ * server takes queued requests first come first served, skipping those
+ * whose job is still busy (a job's requests share its problem state and run
+ * one at a time, in order); up to max_inflight requests of different jobs
+ * run concurrently, each on its job's stream.  Completion is detected with
+ * HIP events; latency = completion - submission (steady clock).
+ *
+ * msfv_server_create : max_inflight in [1, 64].
+ * msfv_server_add_job : registers a caller-owned problem (receivers set;
+ *                     give every job its own stream for concurrency).  The
+ *                     server uses it exclusively until destroyed.
+ * msfv_server_submit : copies the request's sources (host CSR columns, as
+ *                     msfv_set_sources) and queues it; m (N), v (Nr*ns) are
+ *                     device inputs and d_out (Nr*ns), g_out (N) device
+ *                     outputs that must stay valid until the request is done.
+ *                     Returns its id in *req.  EINVAL on bad arguments.
+ * msfv_server_wait   : blocks until request req is done; returns its status
+ *                     and, if latency_ms is not NULL, its latency.
+ * msfv_server_drain  : blocks until every submitted request is done.
+ * msfv_server_stats  : latency percentiles and throughput of the requests
+ *                     completed since the last reset (reset clears them).
+ * msfv_server_destroy: drains, stops the dispatcher, releases the server. */
+typedef struct msfv_server msfv_server;
+typedef struct {
+  long long completed;   /* requests completed since the last reset        */
+  long long failed;      /* of which ended with an error status            */
+  double p50_ms, p90_ms, p99_ms, mean_ms, max_ms;  /* latency              */
+  double span_s;         /* first submission to last completion            */
+  double throughput;     /* completed / span_s (requests per second)       */
+} msfv_serve_stats;
+msfv_status msfv_server_create(int max_inflight, msfv_server** out);
+void msfv_server_destroy(msfv_server* s);
+msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int* job);
+msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, const int* cell,
+                               const double* val, const double* m, const double* v, double* d_out,
+                               double* g_out, long long* req);
+msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms);
+msfv_status msfv_server_drain(msfv_server* s);
+msfv_status msfv_server_stats(msfv_server* s, msfv_serve_stats* out, int reset);
+
 const char* msfv_status_string(msfv_status s);
 const char* msfv_last_error(void);
 

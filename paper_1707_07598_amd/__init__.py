@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (MSFV_BC_LAGRANGE, MSFV_BC_REDUCED, MSFV_COARSE_JACOBI,  # noqa: F401
                    MSFV_COARSE_TWOLEVEL, MsfvError)
 
-__all__ = ["Problem", "Batch", "MSFVForward", "msfv_misfit", "MsfvError"]
+__all__ = ["Problem", "Batch", "Server", "MSFVForward", "msfv_misfit", "MsfvError"]
 
 _MODES = {"reduced": MSFV_BC_REDUCED, "lagrange": MSFV_BC_LAGRANGE}
 _COARSE_PRECONDS = {"twolevel": MSFV_COARSE_TWOLEVEL, "jacobi": MSFV_COARSE_JACOBI,
@@ -375,6 +375,75 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             self.lib.msfv_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving runtime (``msfv_server_*``): forward + J^T v requests of
+    registered jobs, dispatched by a native thread as they arrive, up to
+    ``max_inflight`` jobs at once, each on its job's stream."""
+
+    def __init__(self, max_inflight: int = 8):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.msfv_server_create(int(max_inflight), ctypes.byref(h)), "msfv_server_create")
+        self._h = h
+        self._jobs = []
+        self._live = {}
+
+    def add_job(self, problem: "Problem") -> int:
+        j = ctypes.c_int()
+        _lib.check(self.lib.msfv_server_add_job(self._h, problem._h, ctypes.byref(j)),
+                   "msfv_server_add_job")
+        self._jobs.append(problem)
+        return j.value
+
+    def submit(self, job: int, sources, m, v, d_out, g_out) -> int:
+        """Queue forward + J^T v of job ``job`` with these sources (host
+        CSR-over-columns ptr/cell/val); tensors stay referenced until done."""
+        ptr = np.ascontiguousarray(sources.ptr, dtype=np.int32)
+        cell = np.ascontiguousarray(sources.cell, dtype=np.int32)
+        val = np.ascontiguousarray(sources.val, dtype=np.float64)
+        rid = ctypes.c_longlong()
+        _lib.check(self.lib.msfv_server_submit(
+            self._h, int(job), int(ptr.size - 1),
+            ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            _dptr(m), _dptr(v), _dptr(d_out), _dptr(g_out), ctypes.byref(rid)), "msfv_server_submit")
+        self._live[rid.value] = (m, v, d_out, g_out)
+        return rid.value
+
+    def wait(self, req: int) -> float:
+        """Block until request ``req`` is done; its latency in ms."""
+        lat = ctypes.c_double()
+        try:
+            _lib.check(self.lib.msfv_server_wait(self._h, ctypes.c_longlong(req), ctypes.byref(lat)),
+                       "msfv_server_wait")
+        finally:
+            self._live.pop(req, None)
+        return lat.value
+
+    def drain(self):
+        _lib.check(self.lib.msfv_server_drain(self._h), "msfv_server_drain")
+        self._live.clear()
+
+    def stats(self, reset: bool = False) -> dict:
+        st = _lib.MsfvServeStats()
+        _lib.check(self.lib.msfv_server_stats(self._h, ctypes.byref(st), int(bool(reset))),
+                   "msfv_server_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.msfv_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
 
     def __del__(self):
         try:

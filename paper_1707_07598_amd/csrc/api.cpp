@@ -5,7 +5,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -38,18 +42,27 @@ msfv_status fail(msfv_status s, const std::string& msg) {
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // logical size
+  size_t cap = 0;  // allocated size: a smaller request reuses the allocation
   ~DevBuf() { release(); }
   void release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
-    n = 0;
+    n = cap = 0;
   }
+  // (Re)size; reallocates (which synchronises the device) only to grow.
   hipError_t alloc(size_t count) {
+    if (count <= cap && ptr) {
+      n = count;
+      return hipSuccess;
+    }
     release();
     n = count;
     if (count == 0) return hipSuccess;
-    return hipMalloc(&ptr, count * sizeof(T));
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e == hipSuccess) cap = count;
+    else n = 0;
+    return e;
   }
   // Blocking upload: the host vector may be a temporary.
   hipError_t upload(const std::vector<T>& h, hipStream_t s) {
@@ -1018,6 +1031,279 @@ msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const dou
   b->graphs = best_g;
   if (streams_out) *streams_out = best_s;
   if (graphs_out) *graphs_out = best_g ? 1 : 0;
+  return MSFV_OK;
+}
+
+
+// ---- serving ----------------------------------------------------------------
+
+struct msfv_server {
+  struct Req {
+    int job = 0;
+    Columns src;
+    const double* m = nullptr;
+    const double* v = nullptr;
+    double* d = nullptr;
+    double* g = nullptr;
+    std::chrono::steady_clock::time_point t_submit, t_done;
+    hipEvent_t ev = nullptr;
+    int state = 0;  // 0 queued, 1 running, 2 done
+    msfv_status st = MSFV_OK;
+    std::string err;
+  };
+  std::vector<msfv_problem*> jobs;
+  std::vector<char> busy;
+  std::map<long long, Req> reqs;
+  std::deque<long long> queue;
+  std::vector<long long> running;
+  std::vector<hipEvent_t> ev_pool;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread th;
+  bool stop = false;
+  int max_inflight = 8;
+  int device = 0;
+  long long next_id = 1;
+  // statistics since the last reset
+  std::vector<double> lat_ms;
+  long long failed = 0;
+  bool have_first = false;
+  std::chrono::steady_clock::time_point t_first, t_last;
+
+  void loop();
+  ~msfv_server() {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv_work.notify_all();
+    if (th.joinable()) th.join();
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+// Issue one request on its job's stream (dispatcher thread, lock not held).
+msfv_status serve_issue(msfv_problem* p, msfv_server::Req& r) {
+  if (r.src.count != p->src.count || r.src.ptr != p->src.ptr || r.src.cell != p->src.cell ||
+      r.src.val != p->src.val) {
+    p->src = r.src;
+    p->electrodes_ready = false;
+    p->have_forward = false;
+  }
+  msfv_status st = ensure_ready(p);
+  if (st == MSFV_OK) st = forward_impl(p, r.m, r.d, nullptr);
+  if (st == MSFV_OK) st = jtv_impl(p, r.v, r.g);
+  if (st == MSFV_OK && hipEventRecord(r.ev, p->stream) != hipSuccess)
+    st = fail(MSFV_EDEVICE, "hipEventRecord failed");
+  return st;
+}
+
+}  // namespace
+
+void msfv_server::loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // completions
+    for (size_t k = 0; k < running.size();) {
+      Req& r = reqs[running[k]];
+      const hipError_t q = hipEventQuery(r.ev);
+      if (q == hipErrorNotReady) {
+        ++k;
+        continue;
+      }
+      r.t_done = std::chrono::steady_clock::now();
+      msfv_problem* p = jobs[r.job];
+      lk.unlock();
+      msfv_status st = q == hipSuccess ? check_status(p) : fail(MSFV_EDEVICE, hipGetErrorString(q));
+      std::string err = st == MSFV_OK ? std::string() : std::string(msfv_last_error());
+      lk.lock();
+      r.st = st;
+      r.err = err;
+      r.state = 2;
+      ev_pool.push_back(r.ev);
+      r.ev = nullptr;
+      busy[r.job] = 0;
+      lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
+      if (st != MSFV_OK) ++failed;
+      t_last = r.t_done;
+      running.erase(running.begin() + long(k));
+      cv_done.notify_all();
+    }
+    // dispatch: first queued request whose job is idle
+    bool issued = false;
+    while (int(running.size()) < max_inflight) {
+      auto it = queue.begin();
+      while (it != queue.end() && busy[reqs[*it].job]) ++it;
+      if (it == queue.end()) break;
+      const long long id = *it;
+      queue.erase(it);
+      Req& r = reqs[id];
+      busy[r.job] = 1;
+      r.state = 1;
+      if (ev_pool.empty()) {
+        hipEvent_t e = nullptr;
+        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        ev_pool.push_back(e);
+      }
+      r.ev = ev_pool.back();
+      ev_pool.pop_back();
+      msfv_problem* p = jobs[r.job];
+      lk.unlock();
+      msfv_status st = r.ev ? serve_issue(p, r) : fail(MSFV_EDEVICE, "hipEventCreate failed");
+      std::string err = st == MSFV_OK ? std::string() : std::string(msfv_last_error());
+      lk.lock();
+      issued = true;
+      if (st != MSFV_OK) {  // not running: complete it with its error now
+        r.st = st;
+        r.err = err;
+        r.state = 2;
+        r.t_done = std::chrono::steady_clock::now();
+        if (r.ev) ev_pool.push_back(r.ev);
+        r.ev = nullptr;
+        busy[r.job] = 0;
+        lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
+        ++failed;
+        t_last = r.t_done;
+        cv_done.notify_all();
+        continue;
+      }
+      running.push_back(id);
+    }
+    if (stop && queue.empty() && running.empty()) return;
+    if (issued) continue;
+    if (running.empty())
+      cv_work.wait(lk);
+    else
+      cv_work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+msfv_status msfv_server_create(int max_inflight, msfv_server** out) {
+  if (!out || max_inflight < 1 || max_inflight > 64) return fail(MSFV_EINVAL, "max_inflight outside [1, 64]");
+  *out = nullptr;
+  msfv_server* s = new msfv_server();
+  s->max_inflight = max_inflight;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(MSFV_EDEVICE, "hipGetDevice failed");
+  }
+  s->th = std::thread([s] { s->loop(); });
+  *out = s;
+  return MSFV_OK;
+}
+
+void msfv_server_destroy(msfv_server* s) {
+  if (!s) return;
+  (void)msfv_server_drain(s);
+  delete s;
+}
+
+msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int* job) {
+  if (!s || !p || !job) return fail(MSFV_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (msfv_problem* q : s->jobs)
+    if (q == p) return fail(MSFV_EINVAL, "problem already registered");
+  if (p->rec.count <= 0) return fail(MSFV_ESTATE, "job problem has no receivers");
+  s->jobs.push_back(p);
+  s->busy.push_back(0);
+  *job = int(s->jobs.size()) - 1;
+  return MSFV_OK;
+}
+
+msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, const int* cell,
+                               const double* val, const double* m, const double* v, double* d_out,
+                               double* g_out, long long* req) {
+  if (!s || !m || !v || !d_out || !g_out || !req) return fail(MSFV_EINVAL, "null argument");
+  msfv_problem* p = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (job < 0 || job >= int(s->jobs.size())) return fail(MSFV_EINVAL, "unknown job");
+    p = s->jobs[job];
+  }
+  msfv_server::Req r;
+  msfv_status st = check_columns(p, ns, ptr, cell, val, &r.src);
+  if (st != MSFV_OK) return st;
+  r.job = job;
+  r.m = m;
+  r.v = v;
+  r.d = d_out;
+  r.g = g_out;
+  r.t_submit = std::chrono::steady_clock::now();
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    const long long id = s->next_id++;
+    if (!s->have_first) {
+      s->have_first = true;
+      s->t_first = r.t_submit;
+    }
+    s->reqs.emplace(id, std::move(r));
+    s->queue.push_back(id);
+    *req = id;
+  }
+  s->cv_work.notify_all();
+  return MSFV_OK;
+}
+
+msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms) {
+  if (!s) return fail(MSFV_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req);
+  if (it == s->reqs.end()) return fail(MSFV_EINVAL, "unknown request");
+  s->cv_done.wait(lk, [&] { return it->second.state == 2; });
+  const msfv_status st = it->second.st;
+  const std::string err = it->second.err;
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(it->second.t_done - it->second.t_submit).count();
+  s->reqs.erase(it);
+  lk.unlock();
+  if (st != MSFV_OK) return fail(st, err);
+  return MSFV_OK;
+}
+
+msfv_status msfv_server_drain(msfv_server* s) {
+  if (!s) return fail(MSFV_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->running.empty(); });
+  // forget completed requests nobody waits for
+  for (auto it = s->reqs.begin(); it != s->reqs.end();)
+    it = it->second.state == 2 ? s->reqs.erase(it) : std::next(it);
+  return MSFV_OK;
+}
+
+msfv_status msfv_server_stats(msfv_server* s, msfv_serve_stats* out, int reset) {
+  if (!s || !out) return fail(MSFV_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof *out);
+  std::vector<double> v = s->lat_ms;
+  std::sort(v.begin(), v.end());
+  out->completed = (long long)v.size();
+  out->failed = s->failed;
+  auto pct = [&](double q) {
+    if (v.empty()) return 0.0;
+    const double pos = q * double(v.size() - 1);
+    const size_t i = size_t(pos);
+    const double f = pos - double(i);
+    return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+  };
+  out->p50_ms = pct(0.50);
+  out->p90_ms = pct(0.90);
+  out->p99_ms = pct(0.99);
+  double sum = 0.0;
+  for (double x : v) sum += x;
+  out->mean_ms = v.empty() ? 0.0 : sum / double(v.size());
+  out->max_ms = v.empty() ? 0.0 : v.back();
+  if (s->have_first && !v.empty()) {
+    out->span_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    out->throughput = out->span_s > 0 ? double(v.size()) / out->span_s : 0.0;
+  }
+  if (reset) {
+    s->lat_ms.clear();
+    s->failed = 0;
+    s->have_first = false;
+  }
   return MSFV_OK;
 }
 

@@ -231,14 +231,19 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   __syncthreads();
   const double* b = rhs + size_t(blockIdx.x) * nc;
   double* xo = xout + size_t(blockIdx.x) * nc;
-  double x[RPT], r[RPT], pv[RPT], dinv[RPT];
+  // with many rows a thread the iterate x lives in the output buffer instead
+  // of registers (the per-thread state otherwise spills)
+  constexpr bool LEAN = RPT > 4;
+  double x[LEAN ? 1 : RPT], r[RPT], pv[RPT], dinv[RPT];
   unsigned agg[(RPT + 3) / 4];  // DEFL: aggregate of row q in byte q % 4 of agg[q / 4]
 #pragma unroll
   for (int q = 0; q < (RPT + 3) / 4; ++q) agg[q] = 0u;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int i = threadIdx.x + q * BLOCK;
-    x[q] = r[q] = pv[q] = dinv[q] = 0.0;
+    if (!LEAN) x[q] = 0.0;
+    if (LEAN && i < nc) xo[i] = 0.0;
+    r[q] = pv[q] = dinv[q] = 0.0;
     if (i >= nc || i == 0) continue;  // vertex 0 is fixed: its row and column drop out
     const double dg = kdia[13 * ldk + i];
     dinv[q] = dg > 0.0 ? 1.0 / dg : 0.0;
@@ -324,7 +329,12 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
     const double alpha = pq[0] != 0.0 ? rz / pq[0] : 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      x[q] += alpha * pv[q];
+      if (!LEAN) {
+        x[q] += alpha * pv[q];
+      } else {
+        const int i = threadIdx.x + q * BLOCK;
+        if (i < nc) xo[i] += alpha * pv[q];
+      }
       r[q] -= alpha * ap[q];
     }
     if (DEFL) coarse_correction();
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int i = threadIdx.x + q * BLOCK;
-    if (i < nc) xo[i] = x[q];
+    if (!LEAN && i < nc) xo[i] = x[q];
   }
   if (threadIdx.x == 0) {
     atomicMax(status + kStCoarseMaxIt, it);
@@ -397,7 +407,23 @@ __device__ __forceinline__ double tile_sum(double v, double* red) {
   return t;
 }
 
-__device__ __forceinline__ double sum_parts(const double* part, int ntile) {
+// Sum of ntile per-tile partials by wave 0 (lane l adds tiles l, l+64, ...,
+// then a fixed-order wave sum), broadcast through LDS; call from every thread.
+__device__ __forceinline__ double sum_parts(const double* part, int ntile, double* slot) {
+  if (threadIdx.x < kWave) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < ntile; b += kWave) t += part[b];
+    t = wsum(t);
+    if (threadIdx.x == 0) *slot = t;
+  }
+  __syncthreads();
+  const double v = *slot;
+  __syncthreads();
+  return v;
+}
+
+// the same for the one-thread-per-source start kernel
+__device__ __forceinline__ double sum_parts_serial(const double* part, int ntile) {
   double t = 0.0;
   for (int b = 0; b < ntile; ++b) t += part[b];
   return t;
@@ -431,8 +457,8 @@ __global__ __launch_bounds__(kMT) void k_cgm_init(const double* __restrict__ kdi
 __global__ void k_cgm_start(int ns, int ntile, CgmState S) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ns) return;
-  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile);
-  const double bb = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile);
+  const double rz = sum_parts_serial(S.part + (size_t(1) * ns + j) * ntile, ntile);
+  const double bb = sum_parts_serial(S.part + (size_t(2) * ns + j) * ntile, ntile);
   S.scal[3 * j + 0] = rz;
   S.scal[3 * j + 1] = rz;
   S.scal[3 * j + 2] = bb;
@@ -482,9 +508,10 @@ __global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ k
                                                     int ns, int ntile, int par,
                                                     double* __restrict__ x, CgmState S) {
   __shared__ double red[kMT / kWave];
+  __shared__ double slot;
   const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
   if (S.flag[3 * j + par]) return;  // uniform over the workgroup
-  const double pq = sum_parts(S.part + (size_t(0) * ns + j) * ntile, ntile);
+  const double pq = sum_parts(S.part + (size_t(0) * ns + j) * ntile, ntile, &slot);
   const double alpha = pq != 0.0 ? S.scal[3 * j + par] / pq : 0.0;
   const bool live = i < nc && i != 0;
   double rz = 0.0, rr = 0.0;
@@ -511,6 +538,7 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
                                                      int ns, int ntile, int par, int it, double tol2,
                                                      int maxit, CgmState S, int* status,
                                                      unsigned long long* work) {
+  __shared__ double slot;
   const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
   const int nxt = par ^ 1;
   if (S.flag[3 * j + par]) {
@@ -520,8 +548,8 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
     }
     return;
   }
-  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile);
-  const double rr = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile);
+  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile, &slot);
+  const double rr = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile, &slot);
   const bool conv = rr <= tol2 * S.scal[3 * j + 2];
   const bool bad = rr != rr || (!conv && it >= maxit);
   const bool stop = conv || bad;
