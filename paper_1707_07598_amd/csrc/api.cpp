@@ -141,6 +141,7 @@ struct msfv_problem {
   // two-level coarse preconditioner: aggregates and (Z^T A_k Z)^-1
   msfv::CoarseDefl defl;
   DevBuf<double> d_einv;
+  DevBuf<double> d_mu;  // adjoint local solutions of the wave kernels (per entity 8 x nu)
   // large coarse systems: solver workspace and pinned stop flags
   DevBuf<double> d_cg_ws;
   int* h_flags = nullptr;
@@ -155,7 +156,7 @@ struct msfv_problem {
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
-           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes();
+           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes() + d_mu.bytes();
   }
 };
 
@@ -495,6 +496,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
     set_caps(lp, P.caps_block, P.max_nu_block);
+    lp.mu_scratch = p->d_mu.ptr;
     lp.recv = p->d_faces.ptr;
     lp.push = lagrange ? 0 : 1;
     lp.solve_adj = 1;
@@ -505,6 +507,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp.ents = p->d_faces.ptr;
   lp.nent = int(P.faces.size());
   set_caps(lp, P.caps_face, P.max_nu_face);
+  lp.mu_scratch = p->d_mu.ptr;
   lp.recv = p->d_edges.ptr;
   lp.push = lagrange ? 0 : 1;
   lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
@@ -616,6 +619,15 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   HIP_OR_CLEAN(p->d_kent.alloc(std::max<int64_t>(1, P.kent_size)));
   HIP_OR_CLEAN(p->d_inbuf.alloc(std::max<int64_t>(1, P.inbuf_size)));
   HIP_OR_CLEAN(p->d_W.alloc(size_t(3) * P.ncell));
+  {
+    // scratch of the wave-level adjoint kernels (entities whose lane plane
+    // and column fit one wavefront)
+    auto fits = [](const msfv::Plan::Caps& c) { return c.lane <= 64 && c.col <= 7 && c.nc <= 8; };
+    size_t mu = 0;
+    if (fits(P.caps_block)) mu = std::max(mu, P.blocks.size() * 8 * size_t(std::max(1, P.max_nu_block)));
+    if (fits(P.caps_face)) mu = std::max(mu, P.faces.size() * 8 * size_t(std::max(1, P.max_nu_face)));
+    HIP_OR_CLEAN(p->d_mu.alloc(std::max<size_t>(1, mu)));
+  }
   HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
   HIP_OR_CLEAN(p->d_status.alloc(msfv::kStCount));
   HIP_OR_CLEAN(p->d_work.alloc(8));

@@ -61,6 +61,8 @@ struct LocalParams {
   int push = 1;                    // 1: push loads to lower entities
   int* ent_it = nullptr;                  // per entity: largest CG iteration count of its corners
   unsigned long long* ent_work = nullptr; // per entity, if set: += CG cell-iterations (iterations x own cells)
+  double* mu_scratch = nullptr;           // adjoint: per entity 8 * nu_cap doubles (local adjoint solutions)
+  int uni_cap = 0;                        // wave kernels: doubles of the shared plane-buffer region
 };
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);

@@ -343,25 +343,23 @@ __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[
 struct WaveLds {
   double* sig;
   double* phi;   // basis values of the corners on the closure: phi[c*ncl + i]
-  double* ytab;  // adjoint: y_c = sum_q (M + M^T)_{qc} phi_q on the closure
   double* dsq;
   double* tt;    // 6 * nu (aliases pbuf)
   double* pbuf;  // NWAVE * plane_cap
   double* Mm;
   double* Sm;
-  int* wit;      // per wave: CG iterations of its corner
+  int* wit;      // per corner: CG iterations
   int* sbase;    // adjoint: per side d and corner c, offset of the receiver's load slot (-1: none)
   int* sgeo;     // adjoint: per side, receiver-local index = gx + gy*s1 + gz*s2 + off: {s1, s2, off}
   double* red;   // block reductions (8 waves x 36 values)
 };
 
 template <int NWAVE>
-__device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds, bool adj) {
+__device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
   WaveLds L;
   L.sig = lds;
   L.phi = L.sig + a.sig_cap;
-  L.ytab = L.phi + 8 * a.sig_cap;
-  L.dsq = L.ytab + (adj ? 8 * a.sig_cap : 0);
+  L.dsq = L.phi + 8 * a.sig_cap;
   L.Mm = L.dsq + a.nu_cap;
   L.Sm = L.Mm + 64;
   L.wit = reinterpret_cast<int*>(L.Sm + 64);
@@ -376,8 +374,10 @@ __device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds, bool
 
 // Stage the S_k values of E's corners on E's closure into LDS (one coalesced
 // pass over the closure's CSR rows; corners that are not in a row read 0).
+// With skip_own the entity's own cells are left unset (the forward solve
+// writes them).
 template <int BLOCK>
-__device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* phi) {
+__device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* phi, bool skip_own) {
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   const int nc = E.nc;
   for (int i = threadIdx.x; i < ncl; i += BLOCK) {
@@ -385,6 +385,10 @@ __device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* p
     const int t = i / E.cext[0];
     const int ly = t % E.cext[1];
     const int lz = t / E.cext[1];
+    if (skip_own) {
+      const int ox = E.clo[0] + lx - E.ulo[0], oy = E.clo[1] + ly - E.ulo[1], oz = E.clo[2] + lz - E.ulo[2];
+      if (ox >= 0 && ox < E.uext[0] && oy >= 0 && oy < E.uext[1] && oz >= 0 && oz < E.uext[2]) continue;
+    }
     const int gid = (E.clo[0] + lx) + a.g.s1 * (E.clo[1] + ly) + a.g.s2 * (E.clo[2] + lz);
     const int r0 = a.prow[gid], r1 = a.prow[gid + 1];
     double v[8];
@@ -416,27 +420,37 @@ __device__ __forceinline__ int corner_in(const EntDesc& R, int vid) {
 }
 
 // ---------------------------------------------------------------------------
-template <int NWAVE, int LMAX>
-__global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
+// Forward local solves of one entity per workgroup.  Wave w solves corners
+// w, w + NWAVE, ... (NCMAX corners at most); each solution goes to S_k and
+// into the own-cell entries of the LDS basis table, from which the energy
+// block is formed at the end.  Four waves per block (two corners each) keep
+// two blocks resident per compute unit, so one block's setup and gathers
+// overlap the other's iterations.
+template <int NWAVE, int NCMAX, int LMAX>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds, false);
+  const WaveLds S = carve<NWAVE>(a, lds);
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
-  load_phi_table<BLOCK>(E, a, S.phi);
+  load_phi_table<BLOCK>(E, a, S.phi, !a.prescribe);
   shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ia = lane % w.Ua, ib = lane / w.Ua;
+  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
   const bool valid = lane < w.Ua * w.Ub;
-  const bool active = wid < nc;
   Column<LMAX> C;
-  if (active && !a.prescribe) load_column<LMAX>(E, w, valid, ia, ib, S.tt, C);
+  if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead from here on; pbuf aliases it
   double* pbuf = S.pbuf + wid * a.plane_cap;
-  if (active) {
+#pragma unroll 1
+  for (int c = wid; c < nc; c += NWAVE) {
+    // opaque copies of the lane coordinates: what derives from them is
+    // recomputed in each pass instead of being kept live across passes
+    int ia = ia0, ib = ib0;
+    asm volatile("" : "+v"(ia), "+v"(ib));
     double y[LMAX];
     if (!a.prescribe) {
       // scaled right-hand side: sum over Dirichlet neighbours T phi_c(n)
@@ -448,19 +462,19 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
         cell_masks(E, w, ia, ib, k, &fm, &um);
         const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
         double b = 0.0;
-        #pragma unroll
+#pragma unroll
         for (int dd = 0; dd < 6; ++dd) {
           if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
           const int sgn = (dd & 1) ? 1 : -1;
           const int cn = ci + sgn * cstr(E, dd >> 1);
-          b += harm(S.sig[ci], S.sig[cn]) * S.phi[wid * ncl + cn];
+          b += harm(S.sig[ci], S.sig[cn]) * S.phi[c * ncl + cn];
         }
         y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
       }
       bool ok = true;
       const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
       if (lane == 0) {
-        S.wit[wid] = it;
+        S.wit[c] = it;
         if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
       }
       wave_sync_lds();
@@ -470,18 +484,19 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
       if (!valid || k >= w.L) continue;
       const int u = ia * w.ua + ib * w.ub + k * w.uc;
       const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
       double x;
       if (a.prescribe) {
         int gcv[3];
         gcv[0] = gid % a.g.n[0];
         gcv[1] = (gid / a.g.n[0]) % a.g.n[1];
         gcv[2] = gid / (a.g.n[0] * a.g.n[1]);
-        x = lagrange_value(E, gcv, wid);
+        x = lagrange_value(E, gcv, c);
       } else {
         x = y[k] / S.dsq[u];
       }
-      a.pval[a.prow[gid] + wid] = x;
-      pbuf[u] = x;
+      a.pval[a.prow[gid] + c] = x;
+      S.phi[c * ncl + ci] = x;
     }
   }
   __syncthreads();
@@ -498,7 +513,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
   }
   // energy block K_E = sum over the touched fluxes T dphi dphi^T: one thread
   // per own cell and its owned fluxes, then a fixed-order block reduction
-  constexpr int NQ = NWAVE * (NWAVE + 1) / 2;
+  constexpr int NQ = NCMAX * (NCMAX + 1) / 2;
   double kacc[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) kacc[i] = 0.0;
@@ -509,7 +524,6 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
     int fm, um;
     cell_masks(E, w, ja, jb, k, &fm, &um);
     const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
-    const int u = ja * w.ua + jb * w.ub + k * w.uc;
 #pragma unroll
     for (int dd = 0; dd < 6; ++dd) {
       if (!((fm >> dd) & 1)) continue;
@@ -517,54 +531,70 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_fwd(LocalParams a) {
       if (!(dd & 1) && own) continue;  // counted from the lower own cell
       const int sgn = (dd & 1) ? 1 : -1;
       const int cn = ci + sgn * cstr(E, dd >> 1);
-      const int un = u + sgn * ustr(E, dd >> 1);
       const double T = harm(S.sig[ci], S.sig[cn]);
-      double dp[NWAVE];
+      double dp[NCMAX];
 #pragma unroll
-      for (int q = 0; q < NWAVE; ++q) {
-        dp[q] = 0.0;
-        if (q >= nc) continue;
-        const double pn = own ? S.pbuf[q * a.plane_cap + un] : S.phi[q * ncl + cn];
-        dp[q] = S.pbuf[q * a.plane_cap + u] - pn;
-      }
+      for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
       int qq = 0;
 #pragma unroll
-      for (int q = 0; q < NWAVE; ++q) {
+      for (int q = 0; q < NCMAX; ++q) {
         const double tq = T * dp[q];
 #pragma unroll
-        for (int q2 = q; q2 < NWAVE; ++q2) kacc[qq++] += tq * dp[q2];
+        for (int q2 = q; q2 < NCMAX; ++q2) kacc[qq++] += tq * dp[q2];
       }
     }
   }
   block_sum<NWAVE, NQ>(kacc, S.red);
-  // K_E[q][q2] from the upper triangle, row q at offset q*NWAVE - q(q-1)/2
+  // K_E[q][q2] from the upper triangle, row q at offset q*NCMAX - q(q-1)/2
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
     const int lo = min(q, q2), hi = max(q, q2);
-    a.kent[E.kbase + threadIdx.x] = S.red[lo * NWAVE - lo * (lo - 1) / 2 + (hi - lo)];
+    a.kent[E.kbase + threadIdx.x] = S.red[lo * NCMAX - lo * (lo - 1) / 2 + (hi - lo)];
   }
 }
 
 // ---------------------------------------------------------------------------
-template <int NWAVE, int LMAX>
-__global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
+// Adjoint local solves (source-reduced, transposed) of one entity per
+// workgroup, corners distributed over the waves as in the forward kernel.
+// y_c = sum_q (M + M^T)_{qc} phi_q is formed where it is needed from the LDS
+// basis table; each corner's adjoint solution mu_c goes to the entity's
+// slice of a global scratch (it stays in L2) for the flux weights.
+template <int NWAVE, int NCMAX, int LMAX>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds, true);
+  const WaveLds S = carve<NWAVE>(a, lds);
   const int nc = E.nc;
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
-  load_phi_table<BLOCK>(E, a, S.phi);
-  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
-  if (threadIdx.x < nc * nc) {
-    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+  double* mus = a.mu_scratch + size_t(blockIdx.x) * NCMAX * a.nu_cap;  // mu_c on own cells
+  load_phi_table<BLOCK>(E, a, S.phi, false);
+  // M_E = sum_j t_j lambda_j^T on the corners; t and lambda of the corners
+  // are staged, a chunk of sources at a time, through the plane buffers
+  // before the transmissibilities take that space
+  {
+    double* tl = S.pbuf;
+    const int cap = max(1, a.uni_cap / (2 * nc));  // sources a chunk
     double s = 0.0;
-    for (int j = 0; j < a.ns; ++j)
-      s += a.t[size_t(j) * a.ncoarse + E.vid[q]] * a.lam[size_t(j) * a.ncoarse + E.vid[q2]];
-    S.Mm[threadIdx.x] = s;
+    for (int j0 = 0; j0 < a.ns; j0 += cap) {
+      const int nj = min(cap, a.ns - j0);
+      for (int i = threadIdx.x; i < 2 * nc * nj; i += BLOCK) {
+        const int which = i / (nc * nj), r = i % (nc * nj), q = r / nj, j = r % nj;
+        const double* src = which ? a.lam : a.t;
+        tl[i] = src[size_t(j0 + j) * a.ncoarse + E.vid[q]];
+      }
+      __syncthreads();
+      if (threadIdx.x < nc * nc) {
+        const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+        for (int j = 0; j < nj; ++j) s += tl[q * nj + j] * tl[(nc + q2) * nj + j];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < nc * nc) S.Mm[threadIdx.x] = s;
   }
+  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
@@ -588,24 +618,30 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     }
     S.sbase[threadIdx.x] = base;
   }
-  __syncthreads();
-  // y_c on the closure
-  for (int i = threadIdx.x; i < ncl * nc; i += BLOCK) {
-    const int c = i / ncl, ci = i - c * ncl;
-    double v = 0.0;
-    for (int q = 0; q < nc; ++q) v += S.Sm[q * nc + c] * S.phi[q * ncl + ci];
-    S.ytab[c * ncl + ci] = v;
-  }
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ia = lane % w.Ua, ib = lane / w.Ua;
+  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
   const bool valid = lane < w.Ua * w.Ub;
-  const bool active = wid < nc && a.solve_adj;
+  const bool any = wid < nc && a.solve_adj;
+  __syncthreads();
   Column<LMAX> C;
-  if (active) load_column<LMAX>(E, w, valid, ia, ib, S.tt, C);
+  if (any) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead; pbuf aliases it
   double* pbuf = S.pbuf + wid * a.plane_cap;
-  if (active) {
-    const int c = wid;
+#pragma unroll 1
+  for (int c = a.solve_adj ? wid : nc; c < nc; c += NWAVE) {
+    // opaque copies of the lane coordinates (see the forward kernel)
+    int ia = ia0, ib = ib0;
+    asm volatile("" : "+v"(ia), "+v"(ib));
+    double sc[NCMAX];  // column c of M + M^T
+#pragma unroll
+    for (int q = 0; q < NCMAX; ++q) sc[q] = q < nc ? S.Sm[q * nc + c] : 0.0;
+    auto ycl = [&](int ci) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NCMAX; ++q)
+        if (q < nc) v += sc[q] * S.phi[q * ncl + ci];
+      return v;
+    };
     double y[LMAX];
     // load z_c = pushes + electrode loads - (A^E y_c) on own cells, scaled;
     // the y-part of the pushes to Dirichlet neighbours is written here
@@ -616,13 +652,12 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       int fm, um;
       cell_masks(E, w, ia, ib, k, &fm, &um);
       const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
       const int u = ia * w.ua + ib * w.ub + k * w.uc;
       double z = 0.0;
       for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
       for (int e = E.eptr0; e < E.eptr1; ++e)
         if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
-      const double yu = S.ytab[c * ncl + ci];
+      const double yu = ycl(ci);
 #pragma unroll
       for (int dd = 0; dd < 6; ++dd) {
         if (!((fm >> dd) & 1)) continue;
@@ -630,7 +665,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
         const int sgn = (dd & 1) ? 1 : -1;
         const int cn = ci + sgn * cstr(E, dd >> 1);
         const double T = harm(S.sig[ci], S.sig[cn]);
-        const double dy = yu - S.ytab[c * ncl + cn];
+        const double dy = yu - ycl(cn);
         z -= T * dy;
         if (!own) {
           const int base = S.sbase[dd * 8 + c];
@@ -645,20 +680,20 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       }
       y[k] = z / S.dsq[u];
     }
+    __threadfence_block();  // the y-part stores complete before the mu-part adds below
     bool ok = true;
     const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
     if (lane == 0) {
-      S.wit[wid] = it;
+      S.wit[c] = it;
       if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
     }
-    wave_sync_lds();
-    // mu_c into this wave's buffer; mu-part of the pushes
+    // mu_c to the scratch; mu-part of the pushes
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
       if (!valid || k >= w.L) continue;
       const int u = ia * w.ua + ib * w.ub + k * w.uc;
       const double mu = y[k] / S.dsq[u];
-      pbuf[u] = mu;
+      mus[c * a.nu_cap + u] = mu;
       if (!a.push) continue;
       int fm, um;
       cell_masks(E, w, ia, ib, k, &fm, &um);
@@ -673,11 +708,16 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
         int gc3[3];
         own_coords(E, w, ia, ib, k, gc3);
         gc3[dd >> 1] += sgn;
-        a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
-                 S.sgeo[3 * dd + 2]] += T * mu;
+        // the same thread stored the y-part of this slot before the solve:
+        // a no-return atomic add finishes the sum without a load round trip
+        unsafeAtomicAdd(a.outbuf + base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
+                            S.sgeo[3 * dd + 2],
+                        T * mu);
       }
     }
+    wave_sync_lds();  // the next corner's CG rewrites this wave's buffer
   }
+  __threadfence_block();
   __syncthreads();
   if (threadIdx.x == 0 && a.ent_it) {
     int itm = 0;
@@ -690,7 +730,21 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     a.ent_it[blockIdx.x] = itm;
     if (a.ent_work) a.ent_work[blockIdx.x] += wk;
   }
-  // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for owned fluxes
+  // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for
+  // owned fluxes; the quadratic form uses the symmetric part of M (upper
+  // triangle, off-diagonal entries doubled), held in registers
+  constexpr int NQ = NCMAX * (NCMAX + 1) / 2;
+  double mh[NQ];
+  {
+    int qq = 0;
+#pragma unroll
+    for (int q = 0; q < NCMAX; ++q)
+#pragma unroll
+      for (int q2 = q; q2 < NCMAX; ++q2) {
+        mh[qq] = (q < nc && q2 < nc) ? (q == q2 ? S.Mm[q * nc + q] : S.Sm[q * nc + q2]) : 0.0;
+        ++qq;
+      }
+  }
   const int ncol = w.Ua * w.Ub;
   for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
     const int col = i % ncol, k = i / ncol;
@@ -700,7 +754,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
     const int gid = w.g0 + ja * w.ga + jb * w.gb + k * w.gc;
     const int u = ja * w.ua + jb * w.ub + k * w.uc;
     const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
-    #pragma unroll
+#pragma unroll
     for (int dd = 0; dd < 6; ++dd) {
       if (!((fm >> dd) & 1)) continue;
       const bool own = (um >> dd) & 1;
@@ -709,21 +763,24 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
       const int un = u + sgn * ustr(E, dd >> 1);
       const int gn = gid + sgn * gstr(a.g, dd >> 1);
       const int cn = ci + sgn * cstr(E, dd >> 1);
-      double dp[8];
+      double dp[NCMAX];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
+      for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
       double wv = 0.0;
+      int qq = 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q >= nc) continue;
+      for (int q = 0; q < NCMAX; ++q) {
         double mq = 0.0;
 #pragma unroll
-        for (int q2 = 0; q2 < 8; ++q2)
-          if (q2 < nc) mq += S.Mm[q * nc + q2] * dp[q2];
+        for (int q2 = q; q2 < NCMAX; ++q2) mq += mh[qq++] * dp[q2];
         wv -= dp[q] * mq;
-        if (a.solve_adj) {
-          const double mun = own ? S.pbuf[q * a.plane_cap + un] : 0.0;
-          wv -= (S.pbuf[q * a.plane_cap + u] - mun) * dp[q];
+      }
+      if (a.solve_adj) {
+#pragma unroll
+        for (int q = 0; q < NCMAX; ++q) {
+          if (q >= nc) continue;
+          const double mun = own ? mus[q * a.nu_cap + un] : 0.0;
+          wv -= (mus[q * a.nu_cap + u] - mun) * dp[q];
         }
       }
       const int ax = dd >> 1;
@@ -733,22 +790,25 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_adj(LocalParams a) {
 }
 
 template <int NWAVE>
-size_t wave_lds_bytes(const LocalParams& p, bool adj) {
+size_t wave_lds_bytes(const LocalParams& p) {
   const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
-  return (size_t(adj ? 17 : 9) * p.sig_cap + p.nu_cap + 128 + 40 + 8 * 36 + uni) * sizeof(double);
+  return (size_t(9) * p.sig_cap + p.nu_cap + 128 + 40 + 8 * 36 + uni) * sizeof(double);
 }
 
-template <int NWAVE, int LMAX>
-hipError_t launch_wave_t(const LocalParams& p, bool adj, hipStream_t s) {
-  const size_t lds = wave_lds_bytes<NWAVE>(p, adj);
+template <int NWAVE, int NCMAX, int LMAX>
+hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
+  LocalParams p = pin;
+  p.uni_cap = int(std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap));
+  const size_t lds = wave_lds_bytes<NWAVE>(p);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (adj && !p.mu_scratch) return hipErrorInvalidValue;
   if (adj) {
-    auto kern = k_wave_adj<NWAVE, LMAX>;
+    auto kern = k_wave_adj<NWAVE, NCMAX, LMAX>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
   } else {
-    auto kern = k_wave_fwd<NWAVE, LMAX>;
+    auto kern = k_wave_fwd<NWAVE, NCMAX, LMAX>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
@@ -765,14 +825,15 @@ bool wave_path_fits(const LocalParams& p) {
 hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
   if (!wave_path_fits(p)) return hipErrorInvalidConfiguration;
+  // four waves a workgroup; dual blocks (8 corners) give each wave two
   if (p.nc_cap <= 4) {
-    if (p.col_cap <= 1) return launch_wave_t<4, 1>(p, adj, s);
-    if (p.col_cap <= 3) return launch_wave_t<4, 3>(p, adj, s);
-    return launch_wave_t<4, 7>(p, adj, s);
+    if (p.col_cap <= 1) return launch_wave_t<4, 4, 1>(p, adj, s);
+    if (p.col_cap <= 3) return launch_wave_t<4, 4, 3>(p, adj, s);
+    return launch_wave_t<4, 4, 7>(p, adj, s);
   }
-  if (p.col_cap <= 1) return launch_wave_t<8, 1>(p, adj, s);
-  if (p.col_cap <= 3) return launch_wave_t<8, 3>(p, adj, s);
-  return launch_wave_t<8, 7>(p, adj, s);
+  if (p.col_cap <= 1) return launch_wave_t<4, 8, 1>(p, adj, s);
+  if (p.col_cap <= 3) return launch_wave_t<4, 8, 3>(p, adj, s);
+  return launch_wave_t<4, 8, 7>(p, adj, s);
 }
 
 }  // namespace msfv
