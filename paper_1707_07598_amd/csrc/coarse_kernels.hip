@@ -81,9 +81,9 @@ __device__ __forceinline__ int agg_index(const CoarseDefl& d, int x, int y, int 
 
 // out[a] = sum of stage over the vertices of aggregate a, 16 lanes per
 // aggregate, each lane striding over the box in a fixed order.
-template <int BLOCK>
+template <int BLOCK, typename Pos>
 __device__ __forceinline__ void aggregate_sums(const double* stage, int ncx, int ncy, int ncz,
-                                               const CoarseDefl& d, double* out) {
+                                               const CoarseDefl& d, double* out, Pos pos) {
   const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
   for (int a = grp; a < d.na; a += BLOCK / 16) {
     const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
@@ -93,7 +93,7 @@ __device__ __forceinline__ void aggregate_sums(const double* stage, int ncx, int
     double s = 0.0;
     for (int k = l; k < cnt; k += 16) {
       const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
-      s += stage[x + ncx * (y + ncy * z)];
+      s += stage[pos(x + ncx * (y + ncy * z))];
     }
     s = row16_sum(s);
     if (l == 0) out[a] = s;
@@ -206,10 +206,16 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* __res
 // ---------------------------------------------------------------------------
 // PCG on the 27-diagonal operator, one workgroup per column.  Rows are padded
 // to ldk = RPT*BLOCK (padding rows have zero diagonals); the search direction
-// p lives in LDS with a zero halo of pad = 1 + Ncx + Ncx*Ncy entries on both
-// sides.  With DEFL, the LDS copy of p is reused between the stencil product
-// and the update of p to stage r for the aggregate sums.
-template <int BLOCK, int RPT, bool DEFL>
+// p lives in LDS with a zero halo, so the stencil loop has no branches.
+// Row layouts (QM):
+//  * false: thread t owns rows t + q*BLOCK; p in LDS by row;
+//  * true (RPT | Ncx): thread t owns the RPT consecutive rows RPT*t + q, so
+//    it loads its coefficients of one offset as RPT contiguous doubles and
+//    shares the x-neighbours of its rows; p in LDS as RPT planes,
+//    row RPT*t + q in plane q, slot t (consecutive lanes, consecutive slots).
+// With DEFL, the LDS copy of p is reused between the stencil product and the
+// update of p to stage r for the aggregate sums.
+template <int BLOCK, int RPT, bool DEFL, bool QM>
 __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__ kdia, int ldk, int ncx,
                                                       int ncy, int ncz, const double* __restrict__ rhs,
                                                       double* __restrict__ xout, double rtol, int maxit,
@@ -219,13 +225,23 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   constexpr int NW = BLOCK / kWave;
   const int nc = ncx * ncy * ncz;
   const int pad = 1 + ncx + ncx * ncy;
-  double* p = lds + pad;
-  double* redA = lds + ldk + 2 * pad;
+  const int H = pad / RPT + 2;              // QM: halo slots a plane side
+  const int plane = BLOCK + 2 * H;          // QM: slots a plane
+  const int pn = QM ? RPT * plane : ldk + 2 * pad;
+  double* p = QM ? lds : lds + pad;
+  // LDS position of row i (any row within the halo)
+  auto pos = [=](int i) -> int {
+    if (!QM) return i;
+    const int jj = i + RPT * H;
+    return (jj % RPT) * plane + jj / RPT;
+  };
+  auto row = [=](int q) -> int { return QM ? RPT * int(threadIdx.x) + q : int(threadIdx.x) + q * BLOCK; };
+  double* redA = lds + pn;
   double* redB = redA + NW * 4;
   double* einv = redB + NW * 4;        // DEFL: na * na
   double* sv = einv + (DEFL ? d.na * d.na : 0);  // DEFL: 64
   double* yv = sv + 64;                // DEFL: 64
-  for (int i = threadIdx.x; i < ldk + 2 * pad; i += BLOCK) lds[i] = 0.0;
+  for (int i = threadIdx.x; i < pn; i += BLOCK) lds[i] = 0.0;
   if (DEFL)
     for (int i = threadIdx.x; i < d.na * d.na; i += BLOCK) einv[i] = d.einv[i];
   __syncthreads();
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   for (int q = 0; q < (RPT + 3) / 4; ++q) agg[q] = 0u;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int i = threadIdx.x + q * BLOCK;
+    const int i = row(q);
     if (!LEAN) x[q] = 0.0;
     if (LEAN && i < nc) xo[i] = 0.0;
     r[q] = pv[q] = dinv[q] = 0.0;
@@ -256,9 +272,9 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   // p, which is free between the stencil product and the update of p).
   auto coarse_correction = [&]() {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) p[threadIdx.x + q * BLOCK] = r[q];
+    for (int q = 0; q < RPT; ++q) p[pos(row(q))] = r[q];
     __syncthreads();
-    aggregate_sums<BLOCK>(p, ncx, ncy, ncz, d, sv);
+    aggregate_sums<BLOCK>(p, ncx, ncy, ncz, d, sv, pos);
     __syncthreads();
     if (int(threadIdx.x) < d.na) {
       double y = 0.0;
@@ -289,7 +305,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   const double tol2 = rtol * rtol;
   const bool owns_pin = threadIdx.x == 0;
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) p[threadIdx.x + q * BLOCK] = pv[q];
+  for (int q = 0; q < RPT; ++q) p[pos(row(q))] = pv[q];
   __syncthreads();
   int it = 0;
   bool ok = true;
@@ -309,18 +325,44 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
     int lo = threadIdx.x;
     asm volatile("" : "+s"(kb));
     asm volatile("" : "+v"(lo));
+    if (!QM) {
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-          const int off = dx + ncx * (dy + ncy * dz);
-          const double* kd = kb + size_t(o) * ldk;
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+            const int off = dx + ncx * (dy + ncy * dz);
+            const double* kd = kb + size_t(o) * ldk;
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) ap[q] += kd[q * BLOCK + lo] * p[lo + q * BLOCK + off];
+            for (int q = 0; q < RPT; ++q) ap[q] += kd[q * BLOCK + lo] * p[lo + q * BLOCK + off];
+          }
+    } else {
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          // window w[s] = p(row RPT*t + off + s), s = -1 .. RPT
+          const int slot = lo + H + (ncx * (dy + ncy * dz)) / RPT;
+          double wv[RPT + 2];
+          wv[0] = p[(RPT - 1) * plane + slot - 1];
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) wv[q + 1] = p[q * plane + slot];
+          wv[RPT + 1] = p[slot + 1];
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+            const double2* kd = reinterpret_cast<const double2*>(kb + size_t(o) * ldk) + lo * (RPT / 2);
+#pragma unroll
+            for (int h = 0; h < RPT / 2; ++h) {
+              const double2 kv = kd[h];
+              ap[2 * h] += kv.x * wv[2 * h + 1 + dx];
+              ap[2 * h + 1] += kv.y * wv[2 * h + 2 + dx];
+            }
+          }
         }
+    }
     if (owns_pin) ap[0] = 0.0;
     double pq[1] = {0.0};
 #pragma unroll
@@ -332,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
       if (!LEAN) {
         x[q] += alpha * pv[q];
       } else {
-        const int i = threadIdx.x + q * BLOCK;
+        const int i = row(q);
         if (i < nc) xo[i] += alpha * pv[q];
       }
       r[q] -= alpha * ap[q];
@@ -355,13 +397,13 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       pv[q] = zrow(q) + beta * pv[q];
-      p[threadIdx.x + q * BLOCK] = pv[q];
+      p[pos(row(q))] = pv[q];
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int i = threadIdx.x + q * BLOCK;
+    const int i = row(q);
     if (!LEAN && i < nc) xo[i] = x[q];
   }
   if (threadIdx.x == 0) {
@@ -573,8 +615,15 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
 
 constexpr int kBlock = 1024;
 
-size_t pcg_lds_bytes(int ldk, int pad, int na) {
-  return (size_t(ldk) + 2 * pad + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128) * sizeof(double);
+// RPT consecutive rows a thread (2 or 4, dividing Ncx)
+int qm_rows(int ldk, int ncx) {
+  const int rpt = ldk / kBlock;
+  return ((rpt == 2 || rpt == 4) && ncx % rpt == 0) ? rpt : 0;
+}
+
+size_t pcg_lds_bytes(int ldk, int pad, int na, int qm = 0) {
+  const size_t pn = qm ? size_t(qm) * (kBlock + 2 * (pad / qm + 2)) : size_t(ldk) + 2 * pad;
+  return (pn + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128) * sizeof(double);
 }
 
 size_t setup_lds_bytes(int na) { return size_t(na) * na * sizeof(double); }
@@ -591,7 +640,8 @@ int coarse_ldk(int nc) {
 bool coarse_is_large(const int ncv[3]) {
   const int nc = ncv[0] * ncv[1] * ncv[2];
   const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
-  return nc > 16 * kBlock || pcg_lds_bytes(coarse_ldk(nc), pad, 0) > 160 * 1024;
+  const int ldk = coarse_ldk(nc);
+  return nc > 16 * kBlock || pcg_lds_bytes(ldk, pad, 0, qm_rows(ldk, ncv[0])) > 160 * 1024;
 }
 
 size_t coarse_large_workspace(const int ncv[3], int ns) {
@@ -662,7 +712,7 @@ CoarseDefl coarse_defl_plan(const int ncv[3]) {
   }
   const int nc = ncv[0] * ncv[1] * ncv[2];
   const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
-  d.ok = d.na >= 2 && pcg_lds_bytes(coarse_ldk(nc), pad, d.na) <= 160 * 1024 &&
+  d.ok = d.na >= 2 && pcg_lds_bytes(coarse_ldk(nc), pad, d.na, qm_rows(coarse_ldk(nc), ncv[0])) <= 160 * 1024 &&
          setup_lds_bytes(d.na) <= 160 * 1024;
   return d;
 }
@@ -692,21 +742,24 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
   const int ldk = coarse_ldk(nc);
   const bool use = defl && defl->ok && defl->einv;
   const CoarseDefl d = use ? *defl : CoarseDefl();
-  const size_t lds = pcg_lds_bytes(ldk, pad, use ? d.na : 0);
+  const int qm = qm_rows(ldk, ncv[0]);
+  const size_t lds = pcg_lds_bytes(ldk, pad, use ? d.na : 0, qm);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   const int rpt = ldk / kBlock;
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(ncol), dim3(kBlock), lds, s, kdia, ldk, ncv[0], ncv[1], ncv[2], rhs, x,
+                       rtol, maxit, d, status, work);
+    return hipGetLastError();
+  };
+  if (qm == 2) return use ? go(k_coarse_pcg<kBlock, 2, true, true>) : go(k_coarse_pcg<kBlock, 2, false, true>);
+  if (qm == 4) return use ? go(k_coarse_pcg<kBlock, 4, true, true>) : go(k_coarse_pcg<kBlock, 4, false, true>);
 #define MSFV_PCG_CASE(R)                                                                          \
-  if (rpt <= R) {                                                                                 \
-    auto kern = use ? k_coarse_pcg<kBlock, R, true> : k_coarse_pcg<kBlock, R, false>;             \
-    if (lds > 64 * 1024) {                                                                        \
-      hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));   \
-      if (e != hipSuccess) return e;                                                              \
-    }                                                                                             \
-    hipLaunchKernelGGL(kern, dim3(ncol), dim3(kBlock), lds, s, kdia, ldk, ncv[0], ncv[1], ncv[2], \
-                       rhs, x, rtol, maxit, d, status, work);                                     \
-    return hipGetLastError();                                                                     \
-  }
+  if (rpt <= R) return use ? go(k_coarse_pcg<kBlock, R, true, false>) : go(k_coarse_pcg<kBlock, R, false, false>);
   MSFV_PCG_CASE(1)
   MSFV_PCG_CASE(2)
   MSFV_PCG_CASE(4)

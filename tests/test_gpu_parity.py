@@ -128,6 +128,8 @@ def test_small_2d_workload_parity():
 @pytest.mark.parametrize("n,r,ns", [((40, 36, 32), (4, 4, 4), 1),     # 10 x 9 x 8 vertices
                                     ((40, 36, 32), (4, 4, 4), 20),
                                     ((160, 112), (4, 4), 3),          # 2-D 40 x 28: boxes grow to 8 x 4
+                                    ((176, 160), (4, 4), 2),          # 2-D 44 x 40: two consecutive rows a thread
+                                    ((172, 160), (4, 4), 2),          # 2-D 43 x 40: rows strided (odd Ncx)
                                     ((64, 64), (3, 4), 4)])           # 2-D, 22 x 16
 def test_coarse_preconditioners_parity(n, r, ns):
     """The coarse solvers (two-level aggregate correction, plain Jacobi, and
