@@ -148,6 +148,24 @@ msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double
  * transposed): v device Nr*Ns (same layout as D), g_out device N. */
 msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out);
 
+/* Forward-mode sensitivity J_k(m) dm at the m of the last msfv_forward
+ * (Sec. 4.3 eq. sensred applied to dm, with the tangent of the adaptive basis
+ * of Sec. 4.5): dD = Rx^T (dS_k t + S_k dt), A_k dt = dS_k^T q - dA_k t, where
+ * dS_k is the basis tangent (the local problems differentiated along dm) and
+ * dA_k the Galerkin operator's derivative.  dm: device N; dd_out: device
+ * Nr*Ns (layout of D).  MSFV_ESTATE before a forward; MSFV_EINVAL for
+ * coarsening above 8 (entities wider than one wavefront); MSFV_ENONFINITE
+ * (via msfv_sync) if dm holds NaN or Inf. */
+msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out);
+
+/* The same with the basis held fixed (eq. senssimple, the "fixed" basis of
+ * Fig. 2): dD = -Rx^T S_k A_k^-1 S_k^T (dA/dm dm) u, and its transpose
+ * g = -grad_m sum_j (S_k lambda_j)^T A(m) u_j with lambda = A_k^-1 S_k^T Rx v.
+ * Same arguments and errors as msfv_jvp / msfv_jtv; both use device
+ * workspace of 2 N Ns doubles (allocated on first use). */
+msfv_status msfv_jvp_fixed(msfv_problem* p, const double* dm, double* dd_out);
+msfv_status msfv_jtv_fixed(msfv_problem* p, const double* v, double* g_out);
+
 /* Misfit phi = 1/2 ||D(m) - d_obs||_F^2 (Sec. 2.2) and its gradient
  * J_k^T (D - d_obs): forward + jtv.  phi_out: device, 1 value. */
 msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_obs,

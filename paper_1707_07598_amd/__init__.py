@@ -165,6 +165,28 @@ class Problem:
             self.sync()
         return g
 
+    def jvp(self, dm, out=None, sync: bool = True, fixed: bool = False):
+        """dD = J_k(m) dm at the m of the last forward, as an (Ns, Nr) tensor;
+        ``fixed`` holds the basis S_k fixed (dS = 0)."""
+        torch = _torch()
+        self._check_tensor(dm, int(np.prod(self.n)), "dm")
+        dd = out if out is not None else torch.empty((self._ns, self._nr), dtype=torch.float64, device=dm.device)
+        fn = self.lib.msfv_jvp_fixed if fixed else self.lib.msfv_jvp
+        _lib.check(fn(self._h, _dptr(dm), _dptr(dd)), "msfv_jvp_fixed" if fixed else "msfv_jvp")
+        if sync:
+            self.sync()
+        return dd
+
+    def jtv_fixed(self, v, out=None, sync: bool = True):
+        """g = J_k^T v with the basis S_k held fixed, at the m of the last forward."""
+        torch = _torch()
+        self._check_tensor(v, self._ns * self._nr, "v")
+        g = out if out is not None else torch.empty(int(np.prod(self.n)), dtype=torch.float64, device=v.device)
+        _lib.check(self.lib.msfv_jtv_fixed(self._h, _dptr(v), _dptr(g)), "msfv_jtv_fixed")
+        if sync:
+            self.sync()
+        return g
+
     def misfit_grad(self, m, d_obs, sync: bool = True):
         """(phi, g): phi = 1/2 ||D(m) - d_obs||_F^2 and g = J_k^T (D - d_obs)."""
         torch = _torch()

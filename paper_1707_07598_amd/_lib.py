@@ -82,6 +82,9 @@ SIGNATURES = {
     "msfv_forward": (_I, [_P, _P, _P, _P]),
     "msfv_jtv": (_I, [_P, _P, _P]),
     "msfv_misfit_grad": (_I, [_P, _P, _P, _P, _P]),
+    "msfv_jvp": (_I, [_P, _P, _P]),
+    "msfv_jvp_fixed": (_I, [_P, _P, _P]),
+    "msfv_jtv_fixed": (_I, [_P, _P, _P]),
     "msfv_sync": (_I, [_P]),
     "msfv_get_sizes": (_I, [_P, ctypes.POINTER(MsfvSizes)]),
     "msfv_get_prolongation": (_I, [_P, _IP, _IP, _DP]),

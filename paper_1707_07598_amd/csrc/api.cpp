@@ -142,6 +142,9 @@ struct msfv_problem {
   msfv::CoarseDefl defl;
   DevBuf<double> d_einv;
   DevBuf<double> d_mu;  // adjoint local solutions of the wave kernels (per entity 8 x nu)
+  // sensitivity passes (allocated on first use)
+  DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
+  DevBuf<int> d_ccptr, d_ccidx, d_cccell;  // column lists of S_k
   // large coarse systems: solver workspace and pinned stop flags
   DevBuf<double> d_cg_ws;
   int* h_flags = nullptr;
@@ -156,7 +159,9 @@ struct msfv_problem {
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
-           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes() + d_mu.bytes();
+           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes() + d_mu.bytes() + d_dpval.bytes() +
+           d_dkent.bytes() + d_dkval.bytes() + d_dkdia.bytes() + d_dt.bytes() + d_fu.bytes() +
+           d_fz.bytes() + d_ccptr.bytes() + d_ccidx.bytes() + d_cccell.bytes();
   }
 };
 
@@ -522,6 +527,144 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   return MSFV_OK;
 }
 
+
+// ---- sensitivities: forward-mode J dm and the fixed-basis variants ----------
+
+msfv_status sens_ready(msfv_problem* p) {
+  if (!p->have_forward) return fail(MSFV_ESTATE, "sensitivity call before msfv_forward");
+  const msfv::Plan& P = p->plan;
+  const size_t ncs = size_t(P.ncoarse) * std::max(1, p->src.count);
+  HIP_OK(p->d_dt.alloc(ncs));
+  return MSFV_OK;
+}
+
+msfv_status fine_ready(msfv_problem* p) {
+  const msfv::Plan& P = p->plan;
+  const size_t n = size_t(P.ncell) * std::max(1, p->src.count);
+  HIP_OK(p->d_fu.alloc(n));
+  HIP_OK(p->d_fz.alloc(n));
+  if (!p->d_ccptr.ptr) {  // column lists of S_k (static structure), in increasing cell order
+    const int nc = int(P.ncoarse);
+    std::vector<int> cptr(nc + 1, 0), cidx(P.pcol.size()), ccell(P.pcol.size());
+    for (int c : P.pcol) ++cptr[c + 1];
+    for (int v = 0; v < nc; ++v) cptr[v + 1] += cptr[v];
+    std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t i = 0; i < P.ncell; ++i)
+      for (int e = P.prow[i]; e < P.prow[i + 1]; ++e) {
+        const int k = fill[P.pcol[e]]++;
+        cidx[k] = e;
+        ccell[k] = int(i);
+      }
+    HIP_OK(p->d_ccptr.upload(cptr, p->stream));
+    HIP_OK(p->d_ccidx.upload(cidx, p->stream));
+    HIP_OK(p->d_cccell.upload(ccell, p->stream));
+  }
+  return MSFV_OK;
+}
+
+// J_k dm for the adaptive basis (eq. sensred in forward mode with the basis
+// tangent of Sec. 4.5): dD = Rx^T (dS t + S dt), A_k dt = dS^T q - dA_k t.
+msfv_status jvp_impl(msfv_problem* p, const double* dm, double* dd_out) {
+  msfv_status st = sens_ready(p);
+  if (st != MSFV_OK) return st;
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
+  const int ns = p->src.count, nr = p->rec.count, nc = int(P.ncoarse);
+  if (!p->d_dpval.ptr) {
+    HIP_OK(p->d_dpval.alloc(P.pcol.size()));
+    HIP_OK(hipMemsetAsync(p->d_dpval.ptr, 0, p->d_dpval.bytes(), s));  // vertex rows stay 0
+    HIP_OK(p->d_dkent.alloc(std::max<int64_t>(1, P.kent_size)));
+    HIP_OK(p->d_dkval.alloc(std::max<size_t>(1, P.kcol.size())));
+    HIP_OK(p->d_dkdia.alloc(p->d_kdia.n));
+    HIP_OK(hipMemsetAsync(p->d_dkdia.ptr, 0, p->d_dkdia.bytes(), s));
+  }
+  HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
+  HIP_OK(msfv::launch_check_finite(dm, P.ncell, p->d_status.ptr, s));
+  msfv::LocalParams lp = base_params(p);
+  lp.dm = dm;
+  lp.dpval = p->d_dpval.ptr;
+  lp.kent = p->d_dkent.ptr;
+  lp.ents = p->d_edges.ptr;
+  lp.nent = int(P.edges.size());
+  HIP_OK(msfv::launch_edge_tan(lp, lagrange ? 1 : 0, s));
+  lp.ents = p->d_faces.ptr;
+  lp.nent = int(P.faces.size());
+  set_caps(lp, P.caps_face, P.max_nu_face);
+  lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
+  hipError_t e = msfv::launch_wave_tan(lp, s);
+  if (e == hipErrorInvalidConfiguration)
+    return fail(MSFV_EINVAL, "J dm needs entities that fit one wavefront (coarsening up to 8)");
+  HIP_OK(e);
+  if (P.dim == 3) {
+    lp.ents = p->d_blocks.ptr;
+    lp.nent = int(P.blocks.size());
+    set_caps(lp, P.caps_block, P.max_nu_block);
+    lp.prescribe = 0;
+    e = msfv::launch_wave_tan(lp, s);
+    if (e == hipErrorInvalidConfiguration)
+      return fail(MSFV_EINVAL, "J dm needs entities that fit one wavefront (coarsening up to 8)");
+    HIP_OK(e);
+  }
+  HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_dkent.ptr,
+                                p->d_dkval.ptr, p->d_dkdia.ptr, int(P.kcol.size()), s));
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr, p->d_src_w.ptr,
+                                   nullptr, nullptr, 0, p->d_dpval.ptr, p->d_b.ptr, p->nsrc_slot, 1, nc, s));
+  HIP_OK(msfv::launch_coarse_dk_sub(p->d_dkdia.ptr, msfv::coarse_ldk(nc), P.ncv, ns, p->d_t.ptr,
+                                    p->d_b.ptr, s));
+  HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_dt.ptr, nullptr, s));
+  HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
+                           p->d_pcol.ptr, p->d_dpval.ptr, p->d_t.ptr, nc, dd_out, s, 0));
+  HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
+                           p->d_pcol.ptr, p->d_pval.ptr, p->d_dt.ptr, nc, dd_out, s, 1));
+  return MSFV_OK;
+}
+
+// J dm with the basis held fixed (eq. senssimple): dD = -Rx^T S A_k^-1 S^T (dA u).
+msfv_status jvp_fixed_impl(msfv_problem* p, const double* dm, double* dd_out) {
+  msfv_status st = sens_ready(p);
+  if (st == MSFV_OK) st = fine_ready(p);
+  if (st != MSFV_OK) return st;
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const int ns = p->src.count, nr = p->rec.count, nc = int(P.ncoarse);
+  HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
+  HIP_OK(msfv::launch_check_finite(dm, P.ncell, p->d_status.ptr, s));
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
+                              p->d_fu.ptr, s));
+  HIP_OK(msfv::launch_dAu(p->d_m.ptr, dm, p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, s));
+  HIP_OK(msfv::launch_restrict(p->d_ccptr.ptr, p->d_ccidx.ptr, p->d_cccell.ptr, p->d_pval.ptr, p->d_fz.ptr,
+                               nc, ns, P.ncell, -1.0, p->d_b.ptr, s));
+  HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_dt.ptr, nullptr, s));
+  HIP_OK(msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
+                           p->d_pcol.ptr, p->d_pval.ptr, p->d_dt.ptr, nc, dd_out, s, 0));
+  return MSFV_OK;
+}
+
+// J^T v with the basis held fixed: lambda = A_k^-1 S^T Rx v,
+// g = -grad_m sum_j (S lambda_j)^T A(m) u_j.
+msfv_status jtv_fixed_impl(msfv_problem* p, const double* v, double* g_out) {
+  msfv_status st = sens_ready(p);
+  if (st == MSFV_OK) st = fine_ready(p);
+  if (st != MSFV_OK) return st;
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const int ns = p->src.count, nr = p->rec.count, nc = int(P.ncoarse);
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr, p->d_rec_w.ptr,
+                                   p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr, p->nrec_slot, ns,
+                                   nc, s));
+  HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, nullptr, s));
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
+                              p->d_fu.ptr, s));
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_lam.ptr, nc, ns, P.ncell,
+                              p->d_fz.ptr, s));
+  HIP_OK(msfv::launch_wfixed(p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, p->d_W.ptr, s));
+  HIP_OK(msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
+  return MSFV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -697,6 +840,21 @@ msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double
 msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out) {
   if (!p || !v || !g_out) return fail(MSFV_EINVAL, "null argument");
   return jtv_impl(p, v, g_out);
+}
+
+msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out) {
+  if (!p || !dm || !dd_out) return fail(MSFV_EINVAL, "null argument");
+  return jvp_impl(p, dm, dd_out);
+}
+
+msfv_status msfv_jvp_fixed(msfv_problem* p, const double* dm, double* dd_out) {
+  if (!p || !dm || !dd_out) return fail(MSFV_EINVAL, "null argument");
+  return jvp_fixed_impl(p, dm, dd_out);
+}
+
+msfv_status msfv_jtv_fixed(msfv_problem* p, const double* v, double* g_out) {
+  if (!p || !v || !g_out) return fail(MSFV_EINVAL, "null argument");
+  return jtv_fixed_impl(p, v, g_out);
 }
 
 msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_obs, double* phi_out,

@@ -708,6 +708,67 @@ __global__ void k_edge_fwd(LocalParams a, int lagrange) {
   }
 }
 
+// Tangent of the edge basis along dm (Sec. 4.5, forward mode): with
+// cumulative resistances c_i = sum_{f<i} 1/T_f and R = c_last,
+// phi_hi = c_i / R, phi_lo = 1 - phi_hi, so dphi_hi = (dc_i R - c_i dR) / R^2
+// with dc_i = -sum_{f<i} dT_f / T_f^2.  Strips and Lagrange edges do not depend
+// on m.  Also the tangent energy block dK_E = sum_f dT_f dphi dphi^T +
+// T_f (d(dphi) dphi^T + dphi d(dphi)^T) over the edge's fluxes.
+__global__ void k_edge_tan(LocalParams a, int lagrange) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nent) return;
+  const EntDesc E = a.ents[e];
+  EdgeLine L;
+  edge_line(E, a.g, a.m, L);
+  double cum[kMaxLine], dcum[kMaxLine], dT[kMaxLine];
+  cum[0] = dcum[0] = 0.0;
+  for (int i = 0; i + 1 < L.len; ++i) {
+    const double da = a.dm[L.base + i * L.st], db = a.dm[L.base + (i + 1) * L.st];
+    dT[i] = dharm(L.sig[i], L.sig[i + 1]) * da + dharm(L.sig[i + 1], L.sig[i]) * db;
+    cum[i + 1] = cum[i] + 1.0 / L.T[i];
+    dcum[i + 1] = dcum[i] - dT[i] / (L.T[i] * L.T[i]);
+  }
+  const bool fixed = E.nc == 1 || lagrange;
+  const double R = cum[L.len - 1], dR = dcum[L.len - 1];
+  auto tan = [&](int i, double* d) {
+    if (fixed) {
+      d[0] = d[1] = 0.0;
+      return;
+    }
+    const double d1 = (dcum[i] * R - cum[i] * dR) / (R * R);
+    d[0] = -d1;
+    d[1] = d1;
+  };
+  for (int q = 0; q < E.nu; ++q) {
+    const int i = L.u0 + q;
+    double d[2];
+    tan(i, d);
+    const int row = a.prow[L.base + i * L.st];
+    for (int c = 0; c < E.nc; ++c) a.dpval[row + c] = d[c];
+  }
+  if (E.nc == 1) {
+    a.kent[E.kbase] = 0.0;
+    return;
+  }
+  double k00 = 0.0, k01 = 0.0, k11 = 0.0;
+  for (int i = 0; i + 1 < L.len; ++i) {
+    double pa[2], pb[2], da[2], db[2];
+    edge_phi(E, L, cum, lagrange, i, pa);
+    edge_phi(E, L, cum, lagrange, i + 1, pb);
+    tan(i, da);
+    tan(i + 1, db);
+    const double f0 = pa[0] - pb[0], f1 = pa[1] - pb[1];
+    const double g0 = da[0] - db[0], g1 = da[1] - db[1];
+    k00 += dT[i] * f0 * f0 + 2.0 * L.T[i] * g0 * f0;
+    k01 += dT[i] * f0 * f1 + L.T[i] * (g0 * f1 + f0 * g1);
+    k11 += dT[i] * f1 * f1 + 2.0 * L.T[i] * g1 * f1;
+  }
+  a.kent[E.kbase + 0] = k00;
+  a.kent[E.kbase + 1] = k01;
+  a.kent[E.kbase + 2] = k01;
+  a.kent[E.kbase + 3] = k11;
+}
+
 __global__ void k_edge_adj(LocalParams a, int lagrange) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nent) return;
@@ -848,7 +909,7 @@ __global__ void k_gather_slots(const int* slot_dst, const int* slot_ptr, const i
 
 __global__ void k_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
                        const int* prow, const int* pcol, const double* pval, const double* t, int nc,
-                       double* D) {
+                       double* D, int accumulate) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= nr * ns) return;
   const int i = tid % nr, j = tid / nr;
@@ -860,7 +921,10 @@ __global__ void k_data(const int* rptr, const int* rcell, const double* rval, in
     for (int q = prow[cell]; q < prow[cell + 1]; ++q) uval += pval[q] * tj[pcol[q]];
     acc += rval[e] * uval;
   }
-  D[size_t(j) * nr + i] = acc;
+  if (accumulate)
+    D[size_t(j) * nr + i] += acc;
+  else
+    D[size_t(j) * nr + i] = acc;
 }
 
 __global__ void k_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
@@ -924,6 +988,91 @@ __global__ void k_gfinal(const double* m, const double* W, GridInfo g, long long
     if (c[k] > 0) acc += dharm(si, exp(m[i - st])) * Wk[i - st];
   }
   grad[i] = acc;
+}
+
+// y_j = (dA/dm . dm) u_j: per cell i, sum over its faces f = (i, n) of
+// dT_f (u_j(i) - u_j(n)) with dT_f = dT/dm_i dm_i + dT/dm_n dm_n.
+__global__ void k_dAu(const double* m, const double* dm, GridInfo g, long long ncell, int ns,
+                      const double* u, double* y) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const int c[3] = {int(i % g.n[0]), int((i / g.n[0]) % g.n[1]), int(i / ((long long)g.n[0] * g.n[1]))};
+  const double si = exp(m[i]);
+  double dT[6];
+  long long nb[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int st = gstride_of(g, k);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int q = 2 * k + sd;
+      const bool in = sd ? c[k] + 1 < g.n[k] : c[k] > 0;
+      nb[q] = in ? (sd ? i + st : i - st) : i;
+      const double sn = in ? exp(m[nb[q]]) : si;
+      dT[q] = in ? dharm(si, sn) * dm[i] + dharm(sn, si) * dm[nb[q]] : 0.0;
+    }
+  }
+  for (int j = 0; j < ns; ++j) {
+    const double* uj = u + size_t(j) * ncell;
+    const double ui = uj[i];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += dT[q] * (ui - uj[nb[q]]);
+    y[size_t(j) * ncell + i] = acc;
+  }
+}
+
+// Flux weights of the fixed-basis gradient: W_k(i) = -sum_j (u_j(i) - u_j(n))
+// (z_j(i) - z_j(n)) for the face between i and n = i + e_k.
+__global__ void k_wfixed(GridInfo g, long long ncell, int ns, const double* u, const double* z,
+                         double* W) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const int c[3] = {int(i % g.n[0]), int((i / g.n[0]) % g.n[1]), int(i / ((long long)g.n[0] * g.n[1]))};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double acc = 0.0;
+    if (c[k] + 1 < g.n[k]) {
+      const long long n = i + gstride_of(g, k);
+      for (int j = 0; j < ns; ++j) {
+        const double* uj = u + size_t(j) * ncell;
+        const double* zj = z + size_t(j) * ncell;
+        acc -= (uj[i] - uj[n]) * (zj[i] - zj[n]);
+      }
+    }
+    W[k * ncell + i] = acc;
+  }
+}
+
+// b_j(v) = scale * sum over the column v of S_k of S_k(cell, v) y_j(cell)
+// (column lists: cptr over vertices, cidx = S_k entry, ccell = its row).
+__global__ void k_restrict(const int* cptr, const int* cidx, const int* ccell, const double* pval,
+                           const double* y, int nc, int ns, long long ncell, double scale, double* b) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)nc * ns) return;
+  const int v = int(t % nc), j = int(t / nc);
+  const double* yj = y + size_t(j) * ncell;
+  double acc = 0.0;
+  for (int e = cptr[v]; e < cptr[v + 1]; ++e) acc += pval[cidx[e]] * yj[ccell[e]];
+  b[size_t(j) * nc + v] = scale * acc;
+}
+
+// rhs_j(i) -= sum_o dK[o](i) t_j(i + off_o) on the coarse grid (27 diagonals)
+__global__ void k_coarse_dk_sub(const double* kd, int ldk, int ncx, int ncy, int ncz, int ns,
+                                const double* t, double* rhs) {
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int nc = ncx * ncy * ncz;
+  if (tid >= (long long)nc * ns) return;
+  const int i = int(tid % nc), j = int(tid / nc);
+  const int x = i % ncx, y = (i / ncx) % ncy, z = i / (ncx * ncy);
+  const double* tj = t + size_t(j) * nc;
+  double acc = 0.0;
+  for (int o = 0; o < 27; ++o) {
+    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+    if (x + dx < 0 || x + dx >= ncx || y + dy < 0 || y + dy >= ncy || z + dz < 0 || z + dz >= ncz) continue;
+    acc += kd[size_t(o) * ldk + i] * tj[i + dx + ncx * (dy + ncy * dz)];
+  }
+  rhs[size_t(j) * nc + i] -= acc;
 }
 
 __global__ void k_residual(const double* D, const double* dobs, double* v, long long n,
@@ -1044,11 +1193,11 @@ hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const i
 
 hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
                        const int* prow, const int* pcol, const double* pval, const double* t,
-                       int nc, double* D, hipStream_t s) {
+                       int nc, double* D, hipStream_t s, int accumulate) {
   const int n = nr * ns;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_data, dim3((n + 255) / 256), dim3(256), 0, s, rptr, rcell, rval, nr, ns, prow,
-                     pcol, pval, t, nc, D);
+                     pcol, pval, t, nc, D, accumulate);
   return hipGetLastError();
 }
 
@@ -1074,6 +1223,43 @@ hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long
                          hipStream_t s) {
   hipLaunchKernelGGL(k_gfinal, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, m, W, g, ncell,
                      grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_tan(const LocalParams& p, int lagrange, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_tan, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  return hipGetLastError();
+}
+
+hipError_t launch_dAu(const double* m, const double* dm, GridInfo g, long long ncell, int ns,
+                      const double* u, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_dAu, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, m, dm, g, ncell, ns, u, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_wfixed(GridInfo g, long long ncell, int ns, const double* u, const double* z, double* W,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_wfixed, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, g, ncell, ns, u, z, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const int* cptr, const int* cidx, const int* ccell, const double* pval,
+                           const double* y, int nc, int ns, long long ncell, double scale, double* b,
+                           hipStream_t s) {
+  const long long n = (long long)nc * ns;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, cptr, cidx, ccell, pval, y,
+                     nc, ns, ncell, scale, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_dk_sub(const double* kd, int ldk, const int ncv[3], int ns, const double* t,
+                                double* rhs, hipStream_t s) {
+  const long long n = (long long)ncv[0] * ncv[1] * ncv[2] * ns;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coarse_dk_sub, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, kd, ldk, ncv[0], ncv[1],
+                     ncv[2], ns, t, rhs);
   return hipGetLastError();
 }
 

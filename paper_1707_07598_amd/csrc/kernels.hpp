@@ -63,6 +63,8 @@ struct LocalParams {
   unsigned long long* ent_work = nullptr; // per entity, if set: += CG cell-iterations (iterations x own cells)
   double* mu_scratch = nullptr;           // adjoint: per entity 8 * nu_cap doubles (local adjoint solutions)
   int uni_cap = 0;                        // wave kernels: doubles of the shared plane-buffer region
+  const double* dm = nullptr;             // tangent passes: direction of the model perturbation
+  double* dpval = nullptr;                // tangent passes: dS_k values (CSR of S_k)
 };
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
@@ -123,7 +125,7 @@ hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const i
                                int ncol, int nc, hipStream_t s);
 hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
                        const int* prow, const int* pcol, const double* pval, const double* t,
-                       int nc, double* D, hipStream_t s);
+                       int nc, double* D, hipStream_t s, int accumulate = 0);
 hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
                           int nc, int ns, long long ncell, double* u, hipStream_t s);
 hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
@@ -132,6 +134,24 @@ hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int*
                         const double* v, int nc, int ns, int nr, double* sload, hipStream_t s);
 hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long ncell, double* grad,
                          hipStream_t s);
+// Sensitivity passes (forward-mode J and the fixed-basis variants):
+// tangent edge basis and energy blocks (kent <- dK_E, dpval <- dS on own cells)
+hipError_t launch_edge_tan(const LocalParams& p, int lagrange, hipStream_t s);
+// tangent face / dual-block basis and energy blocks (wave_kernels.hip)
+hipError_t launch_wave_tan(const LocalParams& p, hipStream_t s);
+// y_j = (dA/dm . dm) u_j for all ns columns of u (N each)
+hipError_t launch_dAu(const double* m, const double* dm, GridInfo g, long long ncell, int ns,
+                      const double* u, double* y, hipStream_t s);
+// W_k(i) = -sum_j (u_j(i) - u_j(i+e_k)) (z_j(i) - z_j(i+e_k))
+hipError_t launch_wfixed(GridInfo g, long long ncell, int ns, const double* u, const double* z, double* W,
+                         hipStream_t s);
+// b_j = scale * S_k^T y_j through the column lists of S_k
+hipError_t launch_restrict(const int* cptr, const int* cidx, const int* ccell, const double* pval,
+                           const double* y, int nc, int ns, long long ncell, double scale, double* b,
+                           hipStream_t s);
+// rhs_j -= dK t_j with dK in 27-diagonal storage
+hipError_t launch_coarse_dk_sub(const double* kd, int ldk, const int ncv[3], int ns, const double* t,
+                                double* rhs, hipStream_t s);
 hipError_t launch_residual(const double* D, const double* dobs, double* v, long long n,
                            double* phi, hipStream_t s);
 

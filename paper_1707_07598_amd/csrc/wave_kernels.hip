@@ -27,6 +27,11 @@ namespace {
 constexpr int kWave = 64;
 
 __device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+// d/dm_a of harm(a, b) for sigma = exp(m)
+__device__ __forceinline__ double dharm(double a, double b) {
+  const double s = a + b;
+  return 2.0 * a * b * b / (s * s);
+}
 
 // DPP lane exchange of a double within 16-lane rows.
 template <int CTRL>
@@ -377,7 +382,9 @@ __device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
 // With skip_own the entity's own cells are left unset (the forward solve
 // writes them).
 template <int BLOCK>
-__device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* phi, bool skip_own) {
+__device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* phi, bool skip_own,
+                               const double* vals = nullptr) {
+  const double* pv = vals ? vals : a.pval;
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   const int nc = E.nc;
   for (int i = threadIdx.x; i < ncl; i += BLOCK) {
@@ -396,7 +403,7 @@ __device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* p
     for (int q = 0; q < 8; ++q) v[q] = 0.0;
     for (int e = r0; e < r1; ++e) {
       const int vid = a.pcol[e];
-      const double val = a.pval[e];
+      const double val = pv[e];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (q < nc && E.vid[q] == vid) v[q] = val;
@@ -789,6 +796,129 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Tangent of the face / dual-block basis along dm (Sec. 4.5, forward mode):
+// for each corner c, A^E_UU dphi_c = -(dA^E phi_c)_U - A^E_UB dphi_c|_B, with
+// dA^E the derivative of the entity's reduced operator along dm and dphi_c|_B
+// the tangent of the lower entities (already in dS); then the tangent energy
+// block dK_E = sum over the touched fluxes of dT dphi dphi^T +
+// T (d(dphi) dphi^T + dphi d(dphi)^T).  Prescribed (Lagrange) entities have
+// dphi = 0 and only the dT term.
+template <int NWAVE, int NCMAX, int LMAX>
+__global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
+  extern __shared__ double lds[];
+  constexpr int BLOCK = NWAVE * 64;
+  const EntDesc& E = a.ents[blockIdx.x];
+  const int nc = E.nc;
+  const WGeo w = wave_geo(E, a.g);
+  const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
+  // LDS: sig, phi (8 ncl), dphi (8 ncl), dm (ncl), dsq, small tables, plane buffers
+  WaveLds S = carve<NWAVE>(a, lds);
+  double* dphi = lds + size_t(9) * a.sig_cap + a.nu_cap + 128 + 40 + 8 * 36 + a.uni_cap;
+  double* dmv = dphi + 8 * a.sig_cap;
+  load_phi_table<BLOCK>(E, a, S.phi, false);
+  load_phi_table<BLOCK>(E, a, dphi, false, a.dpval);
+  for (int i = threadIdx.x; i < ncl; i += BLOCK) {
+    const int lx = i % E.cext[0], t = i / E.cext[0];
+    const int ly = t % E.cext[1], lz = t / E.cext[1];
+    dmv[i] = a.dm[(E.clo[0] + lx) + a.g.s1 * (E.clo[1] + ly) + a.g.s2 * (E.clo[2] + lz)];
+  }
+  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  __syncthreads();
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
+  const bool valid = lane < w.Ua * w.Ub;
+  Column<LMAX> C;
+  if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
+  __syncthreads();  // tt is dead; pbuf aliases it
+  double* pbuf = S.pbuf + wid * a.plane_cap;
+  auto dT = [&](int ci, int cn) {
+    return dharm(S.sig[ci], S.sig[cn]) * dmv[ci] + dharm(S.sig[cn], S.sig[ci]) * dmv[cn];
+  };
+#pragma unroll 1
+  for (int c = wid; c < nc; c += NWAVE) {
+    int ia = ia0, ib = ib0;
+    asm volatile("" : "+v"(ia), "+v"(ib));
+    double y[LMAX];
+    if (!a.prescribe) {
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        y[k] = 0.0;
+        if (!valid || k >= w.L) continue;
+        int fm, um;
+        cell_masks(E, w, ia, ib, k, &fm, &um);
+        const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+        const double pc = S.phi[c * ncl + ci];
+        double b = 0.0;
+#pragma unroll
+        for (int dd = 0; dd < 6; ++dd) {
+          if (!((fm >> dd) & 1)) continue;
+          const int sgn = (dd & 1) ? 1 : -1;
+          const int cn = ci + sgn * cstr(E, dd >> 1);
+          b -= dT(ci, cn) * (pc - S.phi[c * ncl + cn]);
+          if (!((um >> dd) & 1)) b += harm(S.sig[ci], S.sig[cn]) * dphi[c * ncl + cn];
+        }
+        y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
+      }
+      bool ok = true;
+      (void)wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+      if (lane == 0 && !ok) atomicAdd(a.status + kStLocalNoconv, 1);
+      wave_sync_lds();
+    }
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      if (!valid || k >= w.L) continue;
+      const int u = ia * w.ua + ib * w.ub + k * w.uc;
+      const int gid = w.g0 + ia * w.ga + ib * w.gb + k * w.gc;
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+      const double x = a.prescribe ? 0.0 : y[k] / S.dsq[u];
+      a.dpval[a.prow[gid] + c] = x;
+      dphi[c * ncl + ci] = x;
+    }
+  }
+  __syncthreads();
+  constexpr int NQ = NCMAX * (NCMAX + 1) / 2;
+  double kacc[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) kacc[i] = 0.0;
+  const int ncol = w.Ua * w.Ub;
+  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
+    const int col = i % ncol, k = i / ncol;
+    const int ja = col % w.Ua, jb = col / w.Ua;
+    int fm, um;
+    cell_masks(E, w, ja, jb, k, &fm, &um);
+    const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
+#pragma unroll
+    for (int dd = 0; dd < 6; ++dd) {
+      if (!((fm >> dd) & 1)) continue;
+      const bool own = (um >> dd) & 1;
+      if (!(dd & 1) && own) continue;  // counted from the lower own cell
+      const int sgn = (dd & 1) ? 1 : -1;
+      const int cn = ci + sgn * cstr(E, dd >> 1);
+      const double T = harm(S.sig[ci], S.sig[cn]);
+      const double dTf = dT(ci, cn);
+      double f[NCMAX], g[NCMAX];
+#pragma unroll
+      for (int q = 0; q < NCMAX; ++q) {
+        f[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
+        g[q] = q < nc ? dphi[q * ncl + ci] - dphi[q * ncl + cn] : 0.0;
+      }
+      int qq = 0;
+#pragma unroll
+      for (int q = 0; q < NCMAX; ++q)
+#pragma unroll
+        for (int q2 = q; q2 < NCMAX; ++q2) kacc[qq++] += dTf * f[q] * f[q2] + T * (g[q] * f[q2] + f[q] * g[q2]);
+    }
+  }
+  block_sum<NWAVE, NQ>(kacc, S.red);
+  if (threadIdx.x < nc * nc) {
+    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+    const int lo = min(q, q2), hi = max(q, q2);
+    a.kent[E.kbase + threadIdx.x] = S.red[lo * NCMAX - lo * (lo - 1) / 2 + (hi - lo)];
+  }
+}
+
 template <int NWAVE>
 size_t wave_lds_bytes(const LocalParams& p) {
   const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
@@ -816,6 +946,20 @@ hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NWAVE, int NCMAX, int LMAX>
+hipError_t launch_tan_t(const LocalParams& pin, hipStream_t s) {
+  LocalParams p = pin;
+  p.uni_cap = int(std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap));
+  const size_t lds = wave_lds_bytes<NWAVE>(p) + (size_t(9) * p.sig_cap) * sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (!p.dm || !p.dpval) return hipErrorInvalidValue;
+  auto kern = k_wave_tan<NWAVE, NCMAX, LMAX>;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool wave_path_fits(const LocalParams& p) {
@@ -834,6 +978,19 @@ hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.col_cap <= 1) return launch_wave_t<4, 8, 1>(p, adj, s);
   if (p.col_cap <= 3) return launch_wave_t<4, 8, 3>(p, adj, s);
   return launch_wave_t<4, 8, 7>(p, adj, s);
+}
+
+hipError_t launch_wave_tan(const LocalParams& p, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!wave_path_fits(p)) return hipErrorInvalidConfiguration;
+  if (p.nc_cap <= 4) {
+    if (p.col_cap <= 1) return launch_tan_t<4, 4, 1>(p, s);
+    if (p.col_cap <= 3) return launch_tan_t<4, 4, 3>(p, s);
+    return launch_tan_t<4, 4, 7>(p, s);
+  }
+  if (p.col_cap <= 1) return launch_tan_t<4, 8, 1>(p, s);
+  if (p.col_cap <= 3) return launch_tan_t<4, 8, 3>(p, s);
+  return launch_tan_t<4, 8, 7>(p, s);
 }
 
 }  // namespace msfv

@@ -1,0 +1,151 @@
+"""Forward-mode sensitivities on the device: J_k dm with the adaptive basis
+(basis tangent, Sec. 4.5), and J dm / J^T v with the basis held fixed (eq.
+senssimple), against the oracle on the parity grids (both boundary modes),
+the dot identity <J dm, v> = <dm, J^T v> on the device, a central finite
+difference of D at the 128^3 benchmark size, and the error paths."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Geometry
+from oracle import reduced as R
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((13, 11, 9), (4, 4, 4)),
+    ((16, 12, 10), (4, 3, 5)),
+    ((17, 9, 12), (8, 3, 4)),
+    ((18, 10, 7), (5, 3, 3)),
+    ((32, 32), (4, 4)),
+    ((23, 17), (5, 6)),
+]
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _problem(n, r, mode, inst):
+    import paper_1707_07598_amd as msfv
+    p = msfv.Problem(n, r, mode)
+    p.set_sources(inst.sources)
+    p.set_receivers(inst.receivers)
+    return p
+
+
+@pytest.mark.parametrize("n,r", CASES)
+@pytest.mark.parametrize("mode", ["reduced", "lagrange"])
+def test_sensitivities_match_oracle(n, r, mode):
+    import torch
+    inst = W.small_instance(n, r, seed=31, ns=3, nr=5)
+    g = Geometry(n, r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers, mode)
+    rng = np.random.default_rng(32)
+    dm = rng.standard_normal(g.ncell)
+    V = rng.standard_normal(st.D.shape)
+    prob = _problem(n, r, mode, inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    prob.forward(m)
+    dmt = torch.tensor(dm, device="cuda")
+    Vt = torch.tensor(V.T.copy(), device="cuda")
+    jv = prob.jvp(dmt).cpu().numpy()
+    assert _rel(jv, R.jvp(st, dm).T) < 1e-8
+    jvf = prob.jvp(dmt, fixed=True).cpu().numpy()
+    assert _rel(jvf, R.jvp_fixed(st, dm).T) < 1e-8
+    gf = prob.jtv_fixed(Vt).cpu().numpy()
+    assert _rel(gf, R.jtv_fixed(st, V)) < 1e-8
+    # dot identities on the device
+    gt = prob.jtv(Vt).cpu().numpy()
+    lhs, rhs = float(np.sum(jv * V.T)), float(dm @ gt)
+    assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), 1e-300) + 1e-14
+    lhs, rhs = float(np.sum(jvf * V.T)), float(dm @ gf)
+    assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), 1e-300) + 1e-14
+    prob.close()
+
+
+def test_sensitivity_fd_at_benchmark_size():
+    import torch
+    inst = W.workload_128()
+    prob = _problem(inst.n, inst.r, "reduced", inst)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    e = torch.tensor(np.random.default_rng(33).standard_normal(m.numel()), device="cuda")
+    h = 1e-5
+    Dp = prob.forward(m + h * e).clone()
+    Dm = prob.forward(m - h * e).clone()
+    fd = ((Dp - Dm) / (2 * h)).cpu().numpy()
+    prob.forward(m)
+    jv = prob.jvp(e).cpu().numpy()
+    assert _rel(jv, fd) < 1e-6
+    jvf = prob.jvp(e, fixed=True).cpu().numpy()
+    # the fixed basis drops dS: a different (and, for this field, worse) approximation
+    assert _rel(jvf, fd) > _rel(jv, fd)
+    s = prob.stats()
+    assert s.local_noconv == 0 and s.coarse_noconv == 0
+    prob.close()
+
+
+def test_sensitivity_errors():
+    import torch
+    import paper_1707_07598_amd as msfv
+    from paper_1707_07598_amd import _lib
+    inst = W.small_instance((13, 11, 9), (4, 4, 4), seed=34, ns=2, nr=3)
+    prob = _problem(inst.n, inst.r, "reduced", inst)
+    dm = torch.ones(int(np.prod(inst.n)), dtype=torch.float64, device="cuda")
+    with pytest.raises(msfv.MsfvError) as e:
+        prob.jvp(dm)
+    assert e.value.status == _lib.MSFV_ESTATE
+    prob.forward(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
+    bad = dm.clone()
+    bad[5] = float("inf")
+    with pytest.raises(msfv.MsfvError) as e:
+        prob.jvp(bad)
+    assert e.value.status == _lib.MSFV_ENONFINITE
+    prob.close()
+    inst16 = W.small_instance((36, 20, 19), (16, 8, 6), seed=35, ns=2, nr=3)
+    p16 = _problem(inst16.n, inst16.r, "reduced", inst16)
+    p16.forward(torch.tensor(inst16.m, dtype=torch.float64, device="cuda"))
+    with pytest.raises(msfv.MsfvError) as e:
+        p16.jvp(torch.ones(int(np.prod(inst16.n)), dtype=torch.float64, device="cuda"))
+    assert e.value.status == _lib.MSFV_EINVAL
+    p16.jvp(torch.ones(int(np.prod(inst16.n)), dtype=torch.float64, device="cuda"), fixed=True)
+    p16.close()
+
+
+def test_fixed_versus_adaptive_two_block_model():
+    """A conductive block (sigma 0.1 in 0.01) on a 36 x 36 x 12 grid, one
+    surface dipole, every cell a receiver (the setting of the paper's
+    sensitivity comparison, Sec. 4): for a perturbation on the block the
+    adaptive J dm is closer to the fine-mesh J dm than the fixed-basis one;
+    for a uniform perturbation both coincide, since S_k(m + c 1) = S_k(m)."""
+    import torch
+    import scipy.sparse as sp
+    import paper_1707_07598_amd as msfv
+    n, r = (36, 36, 12), (6, 6, 6)
+    g = Geometry(n, r)
+    ids = np.arange(g.ncell)
+    x, y, z = ids % 36, (ids // 36) % 36, ids // (36 * 36)
+    blk = (x >= 12) & (x < 24) & (y >= 12) & (y < 24) & (z >= 3) & (z < 9)
+    m = np.where(blk, np.log(0.1), np.log(0.01))
+    src = W.surface_dipoles(n, 1)
+    rec = sp.identity(g.ncell, format="csc")
+    st = R.forward(g, m, src, rec)
+    fs = R.fine_forward(g, m, src, rec)
+    prob = msfv.Problem(n, r, "reduced")
+    prob.set_sources(src)
+    cols = W.SparseColumns(np.arange(g.ncell + 1, dtype=np.int32), ids.astype(np.int32),
+                           np.ones(g.ncell))
+    prob.set_receivers(cols)
+    prob.forward(torch.tensor(m, device="cuda"))
+    errs = {}
+    for name, dm in (("uniform", -0.001 * np.ones(g.ncell)), ("block", -0.001 * blk.astype(float))):
+        dmt = torch.tensor(dm, device="cuda")
+        ja = prob.jvp(dmt).cpu().numpy().T
+        jx = prob.jvp(dmt, fixed=True).cpu().numpy().T
+        assert _rel(ja, R.jvp(st, dm)) < 1e-8 and _rel(jx, R.jvp_fixed(st, dm)) < 1e-8
+        jf = R.fine_jvp(fs, dm)
+        errs[name] = (_rel(ja, jf), _rel(jx, jf), _rel(ja, jx))
+    assert errs["uniform"][2] < 1e-9
+    assert errs["block"][0] < errs["block"][1]
+    prob.close()

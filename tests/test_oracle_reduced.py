@@ -187,3 +187,20 @@ def test_lagrange_skeleton_electrodes_adaptive_equals_fixed(n, r):
     # with reduced boundaries the skeleton moves with m and the two differ
     st_r = R.forward(g, m, src, rec, "reduced")
     assert np.abs(R.jtv(st_r, V) - R.jtv_fixed(st_r, V)).max() > 1e-6 * np.abs(gf).max()
+
+
+@pytest.mark.parametrize("n,r", [((13, 11, 9), (4, 4, 4)), ((20, 14), (5, 4))])
+def test_uniform_perturbation_adaptive_equals_fixed(n, r):
+    """S_k(m + c 1) = S_k(m), so along dm = c 1 the basis tangent vanishes and
+    the adaptive J dm equals the fixed-basis one; both equal -c D (A scales by
+    e^c, u by e^-c)."""
+    from oracle import Geometry
+    from oracle import reduced as R
+    import workloads as W
+    inst = W.small_instance(n, r, seed=36, ns=2, nr=4)
+    g = Geometry(n, r)
+    st = R.forward(g, inst.m, inst.sources, inst.receivers)
+    dm = -0.001 * np.ones(g.ncell)
+    ja, jx = R.jvp(st, dm), R.jvp_fixed(st, dm)
+    assert np.allclose(ja, jx, rtol=1e-10, atol=1e-14 * np.abs(ja).max())
+    assert np.allclose(ja, 0.001 * st.D, rtol=1e-8, atol=1e-12 * np.abs(st.D).max())
