@@ -268,6 +268,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
   for (int i = lane; i < w.plane * w.L; i += kWave) pbuf[i] = 0.0;
   wave_sync_lds();
   const int pidx = (ib + 1) * w.pa + (ia + 1);
+  const int pidx_safe = valid ? pidx : w.pa + 1;
   double r[LMAX], p[LMAX];
   double rr = 0.0;
 #pragma unroll
@@ -294,6 +295,10 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
         if (k < w.L) pbuf[k * w.plane + pidx] = p[k];
     }
     wave_sync_lds();
+    // In-plane neighbours from LDS.  The loads are unconditional so that all
+    // of them issue back to back: lanes outside the plane read an interior
+    // position and planes past the column read the last one, both with zero
+    // coefficients (zero-initialised buffer, finite values).
     double q[LMAX];
     double pq = 0.0;
 #pragma unroll
@@ -301,10 +306,8 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
       double s = p[k];
       if (k > 0) s -= C.tz[k - 1] * p[k - 1];
       if (k + 1 < LMAX) s -= C.tz[k] * p[k + 1];
-      if (valid && k < w.L) {
-        const double* pl = pbuf + k * w.plane + pidx;
-        s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
-      }
+      const double* pl = pbuf + min(k, w.L - 1) * w.plane + pidx_safe;
+      s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
       q[k] = s;
       pq += p[k] * s;
     }
