@@ -25,16 +25,11 @@ namespace {
 
 constexpr int kWave = 64;
 
+// DPP lane exchange of a double within 16-lane rows (every lane written).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -49,9 +44,25 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// v[l] + v[l ^ 16] (ROW32 = false) or v[l] + v[l ^ 32] (ROW32 = true) in every
+// lane, from the gfx950 row-swap instructions applied to two copies of v.
+template <bool ROW32>
+__device__ __forceinline__ double swap_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  if constexpr (ROW32) {
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  } else {
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  }
+}
+
+// Wavefront sum, bitwise identical in every lane.
 __device__ __forceinline__ double wsum(double v) {
-  v = row16_sum(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  return swap_add<true>(swap_add<false>(row16_sum(v)));
 }
 
 // Sum NV values over the workgroup; every thread receives the totals (waves

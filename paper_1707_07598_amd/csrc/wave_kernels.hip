@@ -33,29 +33,41 @@ __device__ __forceinline__ double dharm(double a, double b) {
   return 2.0 * a * b * b / (s * s);
 }
 
-// DPP lane exchange of a double within 16-lane rows.
+// DPP lane exchange of a double within 16-lane rows (every lane written).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
+// v[l] + v[l ^ 16] (ROW32 = false) or v[l] + v[l ^ 32] (ROW32 = true) in every
+// lane: the gfx950 row-swap instructions exchange half of two copies of v,
+// and the two results hold the partner values in complementary halves.
+template <bool ROW32>
+__device__ __forceinline__ double swap_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  if constexpr (ROW32) {
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  } else {
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  }
 }
 
-// Wavefront sum, identical in every lane: exchange within quads (xor 1,
-// xor 2), half rows and rows by DPP, then add the four row sums read from
-// lanes 0, 16, 32, 48 in a fixed order.
+// Wavefront sum, bitwise identical in every lane (each stage adds the same
+// two operands in both partner lanes): exchange within quads (xor 1, xor 2),
+// half rows and rows by DPP, then across row pairs and wave halves.
 __device__ __forceinline__ double wsum(double v) {
   v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);  // row_half_mirror
   v += dpp_move<0x140>(v);  // row_mirror
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  v = swap_add<false>(v);
+  return swap_add<true>(v);
 }
 
 // Block sum of N values per thread in a fixed order: wavefront sums, then
