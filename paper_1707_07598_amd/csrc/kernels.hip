@@ -507,19 +507,17 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
         dp[c] = c < nc ? pu[c] - (own ? a.pval[nbase + c]
                                       : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]))
                        : 0.0;
-      const double tt = cg[j].T[d];
+      // the -(A^E y_c) part of the load is not formed: on own cells it is a
+      // combination of the corner bases' local residuals, zero to the local
+      // solve tolerance; y_c enters only the pushes below
       double quad = 0.0;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         if (c >= nc) continue;
-        double dy = 0.0, mq = 0.0;
+        double mq = 0.0;
 #pragma unroll
-        for (int c2 = 0; c2 < 8; ++c2) {
-          if (c2 >= nc) continue;
-          dy += Sm[c2 * nc + c] * dp[c2];
-          mq += Mm[c * nc + c2] * dp[c2];
-        }
-        zh[j][c] -= tt * dy;
+        for (int c2 = 0; c2 < 8; ++c2)
+          if (c2 < nc) mq += Mm[c * nc + c2] * dp[c2];
         quad += dp[c] * mq;
       }
       if ((d & 1) || !own) wf[j][d] = -quad;

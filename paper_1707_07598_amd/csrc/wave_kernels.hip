@@ -665,8 +665,12 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
       return v;
     };
     double y[LMAX];
-    // load z_c = pushes + electrode loads - (A^E y_c) on own cells, scaled;
-    // the y-part of the pushes to Dirichlet neighbours is written here
+    // load z_c on own cells: the pushes of the entities above and the
+    // electrode loads, scaled.  The -(A^E y_c) part of the load vanishes on
+    // own cells: y_c combines the corner bases, and each of them satisfies
+    // the entity's local problem there (to the local solve tolerance).
+    // Across the fluxes to Dirichlet neighbours y_c enters the pushes, whose
+    // y-part is written here.
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
       y[k] = 0.0;
@@ -679,25 +683,21 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
       for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
       for (int e = E.eptr0; e < E.eptr1; ++e)
         if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
-      const double yu = ycl(ci);
+      if (fm & ~um & 63) {
+        const double yu = ycl(ci);
 #pragma unroll
-      for (int dd = 0; dd < 6; ++dd) {
-        if (!((fm >> dd) & 1)) continue;
-        const bool own = (um >> dd) & 1;
-        const int sgn = (dd & 1) ? 1 : -1;
-        const int cn = ci + sgn * cstr(E, dd >> 1);
-        const double T = harm(S.sig[ci], S.sig[cn]);
-        const double dy = yu - ycl(cn);
-        z -= T * dy;
-        if (!own) {
+        for (int dd = 0; dd < 6; ++dd) {
+          if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
           const int base = S.sbase[dd * 8 + c];
-          if (base >= 0) {
-            int gc3[3];
-            own_coords(E, w, ia, ib, k, gc3);
-            gc3[dd >> 1] += sgn;
-            a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
-                     S.sgeo[3 * dd + 2]] = T * dy;
-          }
+          if (base < 0) continue;
+          const int sgn = (dd & 1) ? 1 : -1;
+          const int cn = ci + sgn * cstr(E, dd >> 1);
+          const double T = harm(S.sig[ci], S.sig[cn]);
+          int gc3[3];
+          own_coords(E, w, ia, ib, k, gc3);
+          gc3[dd >> 1] += sgn;
+          a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] + S.sgeo[3 * dd + 2]] =
+              T * (yu - ycl(cn));
         }
       }
       y[k] = z / S.dsq[u];
@@ -709,10 +709,12 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
       S.wit[c] = it;
       if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
     }
-    // mu_c to the scratch; mu-part of the pushes
+    // mu_c to the scratch; mu-part of the pushes.  A zero load (no
+    // electrodes, no pushes from above) gives mu_c = 0 without iterations:
+    // nothing to store or push, and the flux weights skip the corner.
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
-      if (!valid || k >= w.L) continue;
+      if (it == 0 || !valid || k >= w.L) continue;
       const int u = ia * w.ua + ib * w.ub + k * w.uc;
       const double mu = y[k] / S.dsq[u];
       mus[c * a.nu_cap + u] = mu;
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
       if (a.solve_adj) {
 #pragma unroll
         for (int q = 0; q < NCMAX; ++q) {
-          if (q >= nc) continue;
+          if (q >= nc || S.wit[q] == 0) continue;
           const double mun = own ? mus[q * a.nu_cap + un] : 0.0;
           wv -= (mus[q * a.nu_cap + u] - mun) * dp[q];
         }
