@@ -141,6 +141,7 @@ struct msfv_problem {
   // two-level coarse preconditioner: aggregates and (Z^T A_k Z)^-1
   msfv::CoarseDefl defl;
   DevBuf<double> d_einv;
+  DevBuf<int> d_arows;
   DevBuf<double> d_mu;  // adjoint local solutions of the wave kernels (per entity 8 x nu)
   // sensitivity passes (allocated on first use)
   DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
@@ -159,7 +160,7 @@ struct msfv_problem {
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
            d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
-           d_sload.bytes() + d_einv.bytes() + d_cg_ws.bytes() + d_mu.bytes() + d_dpval.bytes() +
+           d_sload.bytes() + d_einv.bytes() + d_arows.bytes() + d_cg_ws.bytes() + d_mu.bytes() + d_dpval.bytes() +
            d_dkent.bytes() + d_dkval.bytes() + d_dkdia.bytes() + d_dt.bytes() + d_fu.bytes() +
            d_fz.bytes() + d_ccptr.bytes() + d_ccidx.bytes() + d_cccell.bytes();
   }
@@ -755,6 +756,8 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     if (p->defl.ok) {
       HIP_OR_CLEAN(p->d_einv.alloc(size_t(p->defl.na) * p->defl.na));
       p->defl.einv = p->d_einv.ptr;
+      HIP_OR_CLEAN(p->d_arows.upload(msfv::coarse_defl_rows(p->defl, P.ncv), s));
+      p->defl.arows = p->d_arows.ptr;
     }
   }
   HIP_OR_CLEAN(p->d_pval.alloc(P.pcol.size()));

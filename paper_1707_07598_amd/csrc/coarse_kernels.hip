@@ -91,21 +91,16 @@ __device__ __forceinline__ int agg_index(const CoarseDefl& d, int x, int y, int 
 }
 
 // out[a] = sum of stage over the vertices of aggregate a, 16 lanes per
-// aggregate, each lane striding over the box in a fixed order.
+// aggregate, each lane striding over the aggregate's vertex list (from the
+// table d.arows) in a fixed order.
 template <int BLOCK, typename Pos>
-__device__ __forceinline__ void aggregate_sums(const double* stage, int ncx, int ncy, int ncz,
-                                               const CoarseDefl& d, double* out, Pos pos) {
+__device__ __forceinline__ void aggregate_sums(const double* stage, const CoarseDefl& d, double* out, Pos pos) {
   const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int* rows = d.arows + d.na + 1;
   for (int a = grp; a < d.na; a += BLOCK / 16) {
-    const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
-    const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
-    const int w = min(d.b[0], ncx - x0), h = min(d.b[1], ncy - y0), dz = min(d.b[2], ncz - z0);
-    const int cnt = w * h * dz;
+    const int k0 = d.arows[a], k1 = d.arows[a + 1];
     double s = 0.0;
-    for (int k = l; k < cnt; k += 16) {
-      const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
-      s += stage[pos(x + ncx * (y + ncy * z))];
-    }
+    for (int k = k0 + l; k < k1; k += 16) s += stage[pos(rows[k])];
     s = row16_sum(s);
     if (l == 0) out[a] = s;
   }
@@ -285,12 +280,16 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 #pragma unroll
     for (int q = 0; q < RPT; ++q) p[pos(row(q))] = r[q];
     __syncthreads();
-    aggregate_sums<BLOCK>(p, ncx, ncy, ncz, d, sv, pos);
+    aggregate_sums<BLOCK>(p, d, sv, pos);
     __syncthreads();
-    if (int(threadIdx.x) < d.na) {
+    // y = E^-1 s: 16 lanes per row of E^-1 (symmetric, read along a row),
+    // each lane a strided share of the columns, then the row sum
+    for (int t = int(threadIdx.x) >> 4; t < d.na; t += BLOCK / 16) {
+      const int l = threadIdx.x & 15;
       double y = 0.0;
-      for (int c = 0; c < d.na; ++c) y += einv[c * d.na + threadIdx.x] * sv[c];
-      yv[threadIdx.x] = y;
+      for (int c = l; c < d.na; c += 16) y += einv[t * d.na + c] * sv[c];
+      y = row16_sum(y);
+      if (l == 0) yv[t] = y;
     }
     __syncthreads();
   };
@@ -728,6 +727,22 @@ CoarseDefl coarse_defl_plan(const int ncv[3]) {
   return d;
 }
 
+std::vector<int> coarse_defl_rows(const CoarseDefl& d, const int ncv[3]) {
+  std::vector<int> out(size_t(d.na) + 1, 0);
+  out.reserve(out.size() + size_t(ncv[0]) * ncv[1] * ncv[2]);
+  for (int a = 0; a < d.na; ++a) {
+    const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
+    const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
+    const int x1 = std::min(x0 + d.b[0], ncv[0]), y1 = std::min(y0 + d.b[1], ncv[1]),
+              z1 = std::min(z0 + d.b[2], ncv[2]);
+    for (int z = z0; z < z1; ++z)
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) out.push_back(x + ncv[0] * (y + ncv[1] * z));
+    out[size_t(a) + 1] = int(out.size()) - (d.na + 1);
+  }
+  return out;
+}
+
 hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
                                     double* einv, int* status, hipStream_t s) {
   if (!d.ok) return hipErrorInvalidConfiguration;
@@ -751,7 +766,7 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
   const int nc = ncv[0] * ncv[1] * ncv[2];
   const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
   const int ldk = coarse_ldk(nc);
-  const bool use = defl && defl->ok && defl->einv;
+  const bool use = defl && defl->ok && defl->einv && defl->arows;
   const CoarseDefl d = use ? *defl : CoarseDefl();
   const int qm = qm_rows(ldk, ncv[0]);
   const size_t lds = pcg_lds_bytes(ldk, pad, use ? d.na : 0, qm);

@@ -2,6 +2,7 @@
 // kernels.hip, wave_kernels.hip and coarse_kernels.hip).  All pointers are device pointers; every launcher enqueues
 // on ``stream`` and returns the hipError_t of the launch.
 #pragma once
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -93,8 +94,13 @@ struct CoarseDefl {
   int na = 0;
   bool ok = false;              // fits the kernels' LDS budgets
   const double* einv = nullptr; // device, na x na: (Z^T A_k Z)^-1 over the free vertices
+  const int* arows = nullptr;   // device: aggregate offsets (na + 1), then the vertices by aggregate
 };
 CoarseDefl coarse_defl_plan(const int ncv[3]);
+// Host table for CoarseDefl::arows: offsets of each aggregate's vertices
+// (na + 1 entries), then the vertex ids aggregate by aggregate, x fastest
+// within a box.
+std::vector<int> coarse_defl_rows(const CoarseDefl& d, const int ncv[3]);
 // einv = (Z^T A_k Z)^-1 (one workgroup); a non-positive pivot counts as a
 // non-converged coarse solve in status.
 hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
