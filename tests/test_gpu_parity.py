@@ -130,7 +130,9 @@ def test_small_2d_workload_parity():
                                     ((160, 112), (4, 4), 3),          # 2-D 40 x 28: boxes grow to 8 x 4
                                     ((176, 160), (4, 4), 2),          # 2-D 44 x 40: two consecutive rows a thread
                                     ((172, 160), (4, 4), 2),          # 2-D 43 x 40: rows strided (odd Ncx)
-                                    ((64, 64), (3, 4), 4)])           # 2-D, 22 x 16
+                                    ((64, 64), (3, 4), 4),            # 2-D, 22 x 16
+                                    ((128, 64), (4, 4), 3),           # 2-D 32 x 16, odd source count
+                                    ((32, 32, 24), (4, 4, 4), 5)])    # 8 x 8 x 6
 def test_coarse_preconditioners_parity(n, r, ns):
     """The coarse solvers (two-level aggregate correction, plain Jacobi, and
     the multi-launch Jacobi solver of large grids) give D, t and the gradient
