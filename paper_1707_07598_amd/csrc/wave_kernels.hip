@@ -91,6 +91,21 @@ __device__ __forceinline__ void block_sum(const double (&v)[N], double* red) {
   __syncthreads();
 }
 
+// a / b for the CG step lengths.  Short columns (faces) use the hardware
+// reciprocal refined by one Newton step (a few ulp; the iteration only needs
+// the ratio, not its rounding), which measured faster there; long columns
+// keep the full division, which measured faster in the dual-block loop.
+template <int LMAX>
+__device__ __forceinline__ double step_div(double a, double b) {
+  if constexpr (LMAX <= 3) {
+    const double r0 = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, r0, 1.0);
+    return a * fma(r0, e, r0);
+  } else {
+    return a / b;
+  }
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -324,7 +339,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
       pq += p[k] * s;
     }
     pq = wsum(pq);
-    const double alpha = pq != 0.0 ? rr / pq : 0.0;
+    const double alpha = pq != 0.0 ? step_div<LMAX>(rr, pq) : 0.0;
     double rn = 0.0;
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
@@ -338,7 +353,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
       *ok = false;
       break;
     }
-    const double beta = rn / rr;
+    const double beta = step_div<LMAX>(rn, rr);
     rr = rn;
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) p[k] = r[k] + beta * p[k];
