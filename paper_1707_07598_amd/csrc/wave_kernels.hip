@@ -362,6 +362,145 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
   return it;
 }
 
+// Four wavefront sums at once, every lane receiving all four totals.
+// Reduce-scatter: swapping wave halves leaves the half sums of values 0 and
+// 2 (1 and 3) in the low and high halves of one register; swapping odd and
+// even rows then leaves value q's partial in row q; DPP finishes each row,
+// and row q's total is read from lane 16 q.  About a third of the
+// instructions of four separate sums, bitwise deterministic.
+__device__ __forceinline__ void reduce4(double (&v)[4]) {
+  auto swap32_add = [](double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  };
+  auto swap16_add = [](double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  };
+  // lanes 0-31: value 0 (1), lanes 32-63: value 2 (3), each over the two halves
+  const double s02 = swap32_add(v[0], v[2]);
+  const double s13 = swap32_add(v[1], v[3]);
+  // row q (lanes 16q .. 16q + 15): value q over the four rows
+  double t = swap16_add(s02, s13);
+  t += dpp_move<0xB1>(t);   // quad_perm [1,0,3,2]
+  t += dpp_move<0x4E>(t);   // quad_perm [2,3,0,1]
+  t += dpp_move<0x141>(t);  // row_half_mirror
+  t += dpp_move<0x140>(t);  // row_mirror
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(t), 16 * q);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(t), 16 * q);
+    v[q] = __hiloint2double(hi, lo);
+  }
+}
+
+// Conjugate gradients for the (up to) four corners of an entity in lockstep,
+// run by one wavefront: the corners share the operator columns and the loop,
+// and their wave sums go through reduce4.  buf holds four padded plane
+// buffers of plane_cap doubles.  A corner that has converged (or has a zero
+// load) takes zero steps while the others iterate; its[c] and ok[c] report
+// each corner.
+template <int LMAX>
+__device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
+                         double (&y)[4][LMAX], double* buf, int plane_cap, double tol2, int maxit,
+                         int (&its)[4], bool (&ok)[4]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int i = lane; i < 4 * plane_cap; i += kWave) buf[i] = 0.0;
+  wave_sync_lds();
+  const int pidx = (ib + 1) * w.pa + (ia + 1);
+  const int pidx_safe = valid ? pidx : w.pa + 1;
+  double r[4][LMAX], p[4][LMAX], rr[4], bb[4];
+  bool done[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    rr[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      r[c][k] = p[c][k] = y[c][k];
+      y[c][k] = 0.0;
+      rr[c] += r[c][k] * r[c][k];
+    }
+  }
+  reduce4(rr);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    bb[c] = rr[c];
+    done[c] = !(bb[c] > 0.0);
+    its[c] = 0;
+    ok[c] = true;
+  }
+  int it = 0;
+  while (!(done[0] && done[1] && done[2] && done[3])) {
+    if (it >= maxit) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (!done[c]) ok[c] = false, its[c] = it;
+      break;
+    }
+    ++it;
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k)
+          if (k < w.L) buf[c * plane_cap + k * w.plane + pidx] = p[c][k];
+    }
+    wave_sync_lds();
+    double q[4][LMAX], pq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      pq[c] = 0.0;
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        double s = p[c][k];
+        if (k > 0) s -= C.tz[k - 1] * p[c][k - 1];
+        if (k + 1 < LMAX) s -= C.tz[k] * p[c][k + 1];
+        const double* pl = buf + c * plane_cap + min(k, w.L - 1) * w.plane + pidx_safe;
+        s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
+        q[c][k] = s;
+        pq[c] += p[c][k] * s;
+      }
+    }
+    reduce4(pq);
+    double rn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double al = (done[c] || pq[c] == 0.0) ? 0.0 : step_div<LMAX>(rr[c], pq[c]);
+      rn[c] = 0.0;
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        y[c][k] += al * p[c][k];
+        r[c][k] -= al * q[c][k];
+        rn[c] += r[c][k] * r[c][k];
+      }
+    }
+    reduce4(rn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double be = 0.0;
+      if (!done[c]) {
+        if (rn[c] <= tol2 * bb[c]) {
+          done[c] = true;
+          its[c] = it;
+        } else if (rn[c] != rn[c]) {
+          done[c] = true;
+          ok[c] = false;
+          its[c] = it;
+        } else {
+          be = step_div<LMAX>(rn[c], rr[c]);
+          rr[c] = rn[c];
+        }
+      }
+      // a finished corner keeps a zero direction: zero steps, finite products
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) p[c][k] = done[c] ? 0.0 : r[c][k] + be * p[c][k];
+    }
+    wave_sync_lds();  // all lanes finished reading the previous directions
+  }
+}
+
 __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[3], int ci) {
   double v = 1.0;
 #pragma unroll
@@ -386,22 +525,24 @@ struct WaveLds {
   int* wit;      // per corner: CG iterations
   int* sbase;    // adjoint: per side d and corner c, offset of the receiver's load slot (-1: none)
   int* sgeo;     // adjoint: per side, receiver-local index = gx + gy*s1 + gz*s2 + off: {s1, s2, off}
-  double* red;   // block reductions (8 waves x 36 values)
+  double* red;   // block reductions (RED waves x 36 values)
 };
 
-template <int NWAVE>
+// LDS layout: sig, the basis table of PHIC corners, dsq, small tables, the
+// block-reduction scratch of RED waves, then the shared plane-buffer region.
+template <int NWAVE, int PHIC = 8, int RED = 8>
 __device__ __forceinline__ WaveLds carve(const LocalParams& a, double* lds) {
   WaveLds L;
   L.sig = lds;
   L.phi = L.sig + a.sig_cap;
-  L.dsq = L.phi + 8 * a.sig_cap;
+  L.dsq = L.phi + PHIC * a.sig_cap;
   L.Mm = L.dsq + a.nu_cap;
   L.Sm = L.Mm + 64;
   L.wit = reinterpret_cast<int*>(L.Sm + 64);
   L.sbase = L.wit + 8;
   L.sgeo = L.sbase + 48;
   L.red = L.Sm + 64 + 40;
-  double* uni = L.red + 8 * 36;
+  double* uni = L.red + RED * 36;
   L.tt = uni;
   L.pbuf = uni;
   return L;
@@ -468,7 +609,7 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds);
+  const WaveLds S = carve<NWAVE, NCMAX, NWAVE>(a, lds);
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
@@ -481,41 +622,29 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
   Column<LMAX> C;
   if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead from here on; pbuf aliases it
-  double* pbuf = S.pbuf + wid * a.plane_cap;
-#pragma unroll 1
-  for (int c = wid; c < nc; c += NWAVE) {
-    // opaque copies of the lane coordinates: what derives from them is
-    // recomputed in each pass instead of being kept live across passes
-    int ia = ia0, ib = ib0;
-    asm volatile("" : "+v"(ia), "+v"(ib));
-    double y[LMAX];
-    if (!a.prescribe) {
-      // scaled right-hand side: sum over Dirichlet neighbours T phi_c(n)
+  // scaled right-hand side of corner c: sum over Dirichlet neighbours T phi_c(n)
+  auto rhs = [&](int c, int ia, int ib, double (&y)[LMAX]) {
 #pragma unroll
-      for (int k = 0; k < LMAX; ++k) {
-        y[k] = 0.0;
-        if (!valid || k >= w.L) continue;
-        int fm, um;
-        cell_masks(E, w, ia, ib, k, &fm, &um);
-        const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
-        double b = 0.0;
+    for (int k = 0; k < LMAX; ++k) {
+      y[k] = 0.0;
+      if (!valid || k >= w.L) continue;
+      int fm, um;
+      cell_masks(E, w, ia, ib, k, &fm, &um);
+      const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+      double b = 0.0;
 #pragma unroll
-        for (int dd = 0; dd < 6; ++dd) {
-          if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
-          const int sgn = (dd & 1) ? 1 : -1;
-          const int cn = ci + sgn * cstr(E, dd >> 1);
-          b += harm(S.sig[ci], S.sig[cn]) * S.phi[c * ncl + cn];
-        }
-        y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
+        const int sgn = (dd & 1) ? 1 : -1;
+        const int cn = ci + sgn * cstr(E, dd >> 1);
+        b += harm(S.sig[ci], S.sig[cn]) * S.phi[c * ncl + cn];
       }
-      bool ok = true;
-      const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
-      if (lane == 0) {
-        S.wit[c] = it;
-        if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
-      }
-      wave_sync_lds();
+      y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
     }
+  };
+  // corner c's values on the own cells (unscaled solution, or the Lagrange
+  // values of a prescribed entity) to S_k and to the LDS basis table
+  auto store = [&](int c, int ia, int ib, const double (&y)[LMAX]) {
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
       if (!valid || k >= w.L) continue;
@@ -534,6 +663,57 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
       }
       a.pval[a.prow[gid] + c] = x;
       S.phi[c * ncl + ci] = x;
+    }
+  };
+  if constexpr (NWAVE == 1) {
+    // all (at most four) corners in lockstep in the one wave
+    static_assert(NCMAX == 4, "one wave per entity takes four corners");
+    double y[4][LMAX];
+    if (!a.prescribe) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < nc) {
+          rhs(c, ia0, ib0, y[c]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < LMAX; ++k) y[c][k] = 0.0;
+        }
+      }
+      int its[4];
+      bool ok[4];
+      wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (c >= nc) continue;
+          S.wit[c] = its[c];
+          if (!ok[c]) atomicAdd(a.status + kStLocalNoconv, 1);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nc) store(c, ia0, ib0, y[c]);
+  } else {
+    double* pbuf = S.pbuf + wid * a.plane_cap;
+#pragma unroll 1
+    for (int c = wid; c < nc; c += NWAVE) {
+      // opaque copies of the lane coordinates: what derives from them is
+      // recomputed in each pass instead of being kept live across passes
+      int ia = ia0, ib = ib0;
+      asm volatile("" : "+v"(ia), "+v"(ib));
+      double y[LMAX];
+      if (!a.prescribe) {
+        rhs(c, ia, ib, y);
+        bool ok = true;
+        const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+        if (lane == 0) {
+          S.wit[c] = it;
+          if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+        }
+        wave_sync_lds();
+      }
+      store(c, ia, ib, y);
     }
   }
   __syncthreads();
@@ -601,7 +781,7 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
   const EntDesc& E = a.ents[blockIdx.x];
-  const WaveLds S = carve<NWAVE>(a, lds);
+  const WaveLds S = carve<NWAVE, NCMAX, NWAVE>(a, lds);
   const int nc = E.nc;
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
@@ -663,29 +843,21 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
   Column<LMAX> C;
   if (any) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead; pbuf aliases it
-  double* pbuf = S.pbuf + wid * a.plane_cap;
-#pragma unroll 1
-  for (int c = a.solve_adj ? wid : nc; c < nc; c += NWAVE) {
-    // opaque copies of the lane coordinates (see the forward kernel)
-    int ia = ia0, ib = ib0;
-    asm volatile("" : "+v"(ia), "+v"(ib));
-    double sc[NCMAX];  // column c of M + M^T
-#pragma unroll
-    for (int q = 0; q < NCMAX; ++q) sc[q] = q < nc ? S.Sm[q * nc + c] : 0.0;
+  // load z_c on own cells: the pushes of the entities above and the
+  // electrode loads, scaled.  The -(A^E y_c) part of the load vanishes on
+  // own cells: y_c = sum_q (M + M^T)_{qc} phi_q combines the corner bases,
+  // and each of them satisfies the entity's local problem there (to the
+  // local solve tolerance).  Across the fluxes to Dirichlet neighbours y_c
+  // enters the pushes, whose y-part is written here.
+  auto load = [&](int c, int ia, int ib, double (&y)[LMAX]) {
+    // y_c at closure cell ci (column c of M + M^T read from LDS)
     auto ycl = [&](int ci) {
       double v = 0.0;
 #pragma unroll
       for (int q = 0; q < NCMAX; ++q)
-        if (q < nc) v += sc[q] * S.phi[q * ncl + ci];
+        if (q < nc) v += S.Sm[q * nc + c] * S.phi[q * ncl + ci];
       return v;
     };
-    double y[LMAX];
-    // load z_c on own cells: the pushes of the entities above and the
-    // electrode loads, scaled.  The -(A^E y_c) part of the load vanishes on
-    // own cells: y_c combines the corner bases, and each of them satisfies
-    // the entity's local problem there (to the local solve tolerance).
-    // Across the fluxes to Dirichlet neighbours y_c enters the pushes, whose
-    // y-part is written here.
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
       y[k] = 0.0;
@@ -717,16 +889,11 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
       }
       y[k] = z / S.dsq[u];
     }
-    __threadfence_block();  // the y-part stores complete before the mu-part adds below
-    bool ok = true;
-    const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
-    if (lane == 0) {
-      S.wit[c] = it;
-      if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
-    }
-    // mu_c to the scratch; mu-part of the pushes.  A zero load (no
-    // electrodes, no pushes from above) gives mu_c = 0 without iterations:
-    // nothing to store or push, and the flux weights skip the corner.
+  };
+  // mu_c to the scratch; mu-part of the pushes.  A zero load (no
+  // electrodes, no pushes from above) gives mu_c = 0 without iterations:
+  // nothing to store or push, and the flux weights skip the corner.
+  auto finish = [&](int c, int ia, int ib, const double (&y)[LMAX], int it) {
 #pragma unroll
     for (int k = 0; k < LMAX; ++k) {
       if (it == 0 || !valid || k >= w.L) continue;
@@ -754,7 +921,131 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
                         T * mu);
       }
     }
-    wave_sync_lds();  // the next corner's CG rewrites this wave's buffer
+  };
+  if constexpr (NWAVE == 1) {
+    // all (at most four) corners in lockstep in the one wave
+    static_assert(NCMAX == 4, "one wave per entity takes four corners");
+    if (a.solve_adj) {
+      double y[4][LMAX];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < nc) {
+          load(c, ia0, ib0, y[c]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < LMAX; ++k) y[c][k] = 0.0;
+        }
+      }
+      __threadfence_block();  // the y-part stores complete before the mu-part adds below
+      int its[4];
+      bool ok[4];
+      wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (c >= nc) continue;
+          S.wit[c] = its[c];
+          if (!ok[c]) atomicAdd(a.status + kStLocalNoconv, 1);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < nc) finish(c, ia0, ib0, y[c], its[c]);
+    }
+  } else {
+    double* pbuf = S.pbuf + wid * a.plane_cap;
+  #pragma unroll 1
+    for (int c = a.solve_adj ? wid : nc; c < nc; c += NWAVE) {
+      // opaque copies of the lane coordinates (see the forward kernel)
+      int ia = ia0, ib = ib0;
+      asm volatile("" : "+v"(ia), "+v"(ib));
+      double sc[NCMAX];  // column c of M + M^T
+  #pragma unroll
+      for (int q = 0; q < NCMAX; ++q) sc[q] = q < nc ? S.Sm[q * nc + c] : 0.0;
+      auto ycl = [&](int ci) {
+        double v = 0.0;
+  #pragma unroll
+        for (int q = 0; q < NCMAX; ++q)
+          if (q < nc) v += sc[q] * S.phi[q * ncl + ci];
+        return v;
+      };
+      double y[LMAX];
+      // load z_c on own cells: the pushes of the entities above and the
+      // electrode loads, scaled.  The -(A^E y_c) part of the load vanishes on
+      // own cells: y_c combines the corner bases, and each of them satisfies
+      // the entity's local problem there (to the local solve tolerance).
+      // Across the fluxes to Dirichlet neighbours y_c enters the pushes, whose
+      // y-part is written here.
+  #pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        y[k] = 0.0;
+        if (!valid || k >= w.L) continue;
+        int fm, um;
+        cell_masks(E, w, ia, ib, k, &fm, &um);
+        const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+        const int u = ia * w.ua + ib * w.ub + k * w.uc;
+        double z = 0.0;
+        for (int s = 0; s < E.nslot; ++s) z += a.inbuf[E.inbase + (s * nc + c) * E.nu + u];
+        for (int e = E.eptr0; e < E.eptr1; ++e)
+          if (a.eloc[e] == u) z += a.sload[a.eidx[e] * 8 + c];
+        if (fm & ~um & 63) {
+          const double yu = ycl(ci);
+  #pragma unroll
+          for (int dd = 0; dd < 6; ++dd) {
+            if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
+            const int base = S.sbase[dd * 8 + c];
+            if (base < 0) continue;
+            const int sgn = (dd & 1) ? 1 : -1;
+            const int cn = ci + sgn * cstr(E, dd >> 1);
+            const double T = harm(S.sig[ci], S.sig[cn]);
+            int gc3[3];
+            own_coords(E, w, ia, ib, k, gc3);
+            gc3[dd >> 1] += sgn;
+            a.outbuf[base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] + S.sgeo[3 * dd + 2]] =
+                T * (yu - ycl(cn));
+          }
+        }
+        y[k] = z / S.dsq[u];
+      }
+      __threadfence_block();  // the y-part stores complete before the mu-part adds below
+      bool ok = true;
+      const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+      if (lane == 0) {
+        S.wit[c] = it;
+        if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+      }
+      // mu_c to the scratch; mu-part of the pushes.  A zero load (no
+      // electrodes, no pushes from above) gives mu_c = 0 without iterations:
+      // nothing to store or push, and the flux weights skip the corner.
+  #pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        if (it == 0 || !valid || k >= w.L) continue;
+        const int u = ia * w.ua + ib * w.ub + k * w.uc;
+        const double mu = y[k] / S.dsq[u];
+        mus[c * a.nu_cap + u] = mu;
+        if (!a.push) continue;
+        int fm, um;
+        cell_masks(E, w, ia, ib, k, &fm, &um);
+        const int ci = w.s0 + ia * w.sa + ib * w.sb + k * w.sc;
+  #pragma unroll
+        for (int dd = 0; dd < 6; ++dd) {
+          if (!((fm >> dd) & 1) || ((um >> dd) & 1)) continue;
+          const int base = S.sbase[dd * 8 + c];
+          if (base < 0) continue;
+          const int sgn = (dd & 1) ? 1 : -1;
+          const double T = harm(S.sig[ci], S.sig[ci + sgn * cstr(E, dd >> 1)]);
+          int gc3[3];
+          own_coords(E, w, ia, ib, k, gc3);
+          gc3[dd >> 1] += sgn;
+          // the same thread stored the y-part of this slot before the solve:
+          // a no-return atomic add finishes the sum without a load round trip
+          unsafeAtomicAdd(a.outbuf + base + gc3[0] + S.sgeo[3 * dd] * gc3[1] + S.sgeo[3 * dd + 1] * gc3[2] +
+                              S.sgeo[3 * dd + 2],
+                          T * mu);
+        }
+      }
+      wave_sync_lds();  // the next corner's CG rewrites this wave's buffer
+    }
   }
   __threadfence_block();
   __syncthreads();
@@ -951,17 +1242,18 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
   }
 }
 
-template <int NWAVE>
+template <int NWAVE, int PHIC = 8, int RED = 8>
 size_t wave_lds_bytes(const LocalParams& p) {
-  const size_t uni = std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap);
-  return (size_t(9) * p.sig_cap + p.nu_cap + 128 + 40 + 8 * 36 + uni) * sizeof(double);
+  return (size_t(1 + PHIC) * p.sig_cap + p.nu_cap + 128 + 40 + RED * 36 + size_t(p.uni_cap)) * sizeof(double);
 }
 
 template <int NWAVE, int NCMAX, int LMAX>
 hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
   LocalParams p = pin;
-  p.uni_cap = int(std::max(size_t(6) * p.nu_cap, size_t(NWAVE) * p.plane_cap));
-  const size_t lds = wave_lds_bytes<NWAVE>(p);
+  // plane buffers: one a wave, or four (one a corner) for the one-wave path
+  const size_t bufs = NWAVE == 1 ? 4 : NWAVE;
+  p.uni_cap = int(std::max(size_t(6) * p.nu_cap, bufs * p.plane_cap));
+  const size_t lds = wave_lds_bytes<NWAVE, NCMAX, NWAVE>(p);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (adj && !p.mu_scratch) return hipErrorInvalidValue;
   if (adj) {
@@ -1001,9 +1293,10 @@ bool wave_path_fits(const LocalParams& p) {
 hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
   if (!wave_path_fits(p)) return hipErrorInvalidConfiguration;
-  // four waves a workgroup; dual blocks (8 corners) give each wave two
+  // four waves a workgroup; dual blocks (8 corners) give each wave two;
+  // faces (one cell a lane, four corners) run their corners in one wave
   if (p.nc_cap <= 4) {
-    if (p.col_cap <= 1) return launch_wave_t<4, 4, 1>(p, adj, s);
+    if (p.col_cap <= 1) return launch_wave_t<1, 4, 1>(p, adj, s);
     if (p.col_cap <= 3) return launch_wave_t<4, 4, 3>(p, adj, s);
     return launch_wave_t<4, 4, 7>(p, adj, s);
   }
