@@ -216,7 +216,7 @@ __device__ __forceinline__ void own_coords(const EntDesc& E, const WGeo& w, int 
 // sigma on the closure, sqrt of the operator diagonal, scaled transmissibilities
 template <int BLOCK>
 __device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* __restrict__ m,
-                             double* sig, double* dsq, double* tt, const WGeo& w) {
+                             double* sig, double* dsq, double* tt, const WGeo& w, bool op = true) {
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   for (int i = threadIdx.x; i < ncl; i += BLOCK) {
     const int lx = i % E.cext[0];
@@ -226,6 +226,7 @@ __device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* 
     sig[i] = exp(m[(E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz)]);
   }
   __syncthreads();
+  if (!op) return;  // sigma only: no local solve follows
   const int ncol = w.Ua * w.Ub;
   for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
     const int col = i % ncol, k = i / ncol;
@@ -811,7 +812,11 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
     }
     if (threadIdx.x < nc * nc) S.Mm[threadIdx.x] = s;
   }
-  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  // an entity with no electrode loads and no pushes from above has zero
+  // adjoint loads (dual blocks off the electrodes): no local operator, no
+  // solve, only the pushes of y_c and the flux weights
+  const bool loaded = a.solve_adj && (E.nslot > 0 || E.eptr1 > E.eptr0);
+  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w, loaded);
   __syncthreads();
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
@@ -838,7 +843,7 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
   const bool valid = lane < w.Ua * w.Ub;
-  const bool any = wid < nc && a.solve_adj;
+  const bool any = wid < nc && loaded;
   __syncthreads();
   Column<LMAX> C;
   if (any) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
@@ -887,7 +892,7 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
               T * (yu - ycl(cn));
         }
       }
-      y[k] = z / S.dsq[u];
+      y[k] = loaded ? z / S.dsq[u] : 0.0;
     }
   };
   // mu_c to the scratch; mu-part of the pushes.  A zero load (no
@@ -937,9 +942,10 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
         }
       }
       __threadfence_block();  // the y-part stores complete before the mu-part adds below
-      int its[4];
-      bool ok[4];
-      wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+      int its[4] = {0, 0, 0, 0};
+      bool ok[4] = {true, true, true, true};
+      if (loaded)
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -1005,11 +1011,11 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
                 T * (yu - ycl(cn));
           }
         }
-        y[k] = z / S.dsq[u];
+        y[k] = loaded ? z / S.dsq[u] : 0.0;
       }
       __threadfence_block();  // the y-part stores complete before the mu-part adds below
       bool ok = true;
-      const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+      const int it = loaded ? wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok) : 0;
       if (lane == 0) {
         S.wit[c] = it;
         if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
