@@ -193,6 +193,81 @@ __device__ __forceinline__ void cell_masks(const EntDesc& E, const WGeo& w, int 
   *um = u & f;
 }
 
+// The fine fluxes an entity owns as a flat list that a workgroup strides
+// through in step: for each open axis k, the +k flux of every own cell (to
+// an own cell, or on the upper face to a closure cell), then the -k flux of
+// the own cells on the lower face (to a closure cell).  Consecutive items
+// share a direction, so the lanes of a wave take the same branch; a flux
+// that would leave the closure (the domain boundary) comes back invalid.
+struct OwnedFlux {
+  int u, ci, gid;  // own cell: own index, closure index, global id
+  int ax, sgn;     // direction of the flux from the own cell
+  bool own;        // the neighbour is an own cell
+  bool valid;
+};
+
+__device__ __forceinline__ int owned_flux_count(const EntDesc& E) {
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if ((E.open_mask >> k) & 1) n += E.nu + E.nu / sel3(k, E.uext[0], E.uext[1], E.uext[2]);
+  return n;
+}
+
+__device__ __forceinline__ OwnedFlux owned_flux(const EntDesc& E, const GridInfo& g, int g0, int item) {
+  OwnedFlux f;
+  f.valid = false;
+  const int e0 = E.uext[0], e1 = E.uext[1], e2 = E.uext[2];
+  int ax = -1, sgn = 1, idx = item;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (ax >= 0 || !((E.open_mask >> k) & 1)) continue;
+    const int face = E.nu / sel3(k, e0, e1, e2);
+    if (idx < E.nu) {
+      ax = k;
+      sgn = 1;
+    } else if (idx < E.nu + face) {
+      ax = k;
+      sgn = -1;
+      idx -= E.nu;
+    } else {
+      idx -= E.nu + face;
+    }
+  }
+  if (ax < 0) return f;
+  int ux, uy, uz;
+  if (sgn > 0) {
+    ux = idx % e0;
+    const int t = idx / e0;
+    uy = t % e1;
+    uz = t / e1;
+  } else if (ax == 0) {
+    ux = 0;
+    uy = idx % e1;
+    uz = idx / e1;
+  } else if (ax == 1) {
+    ux = idx % e0;
+    uy = 0;
+    uz = idx / e0;
+  } else {
+    ux = idx % e0;
+    uy = idx / e0;
+    uz = 0;
+  }
+  const int o0 = E.ulo[0] - E.clo[0], o1 = E.ulo[1] - E.clo[1], o2 = E.ulo[2] - E.clo[2];
+  const int own = sel3(ax, ux, uy, uz);
+  const int cl = own + sel3(ax, o0, o1, o2);
+  const int cext = sel3(ax, E.cext[0], E.cext[1], E.cext[2]);
+  f.valid = sgn > 0 ? cl + 1 < cext : cl - 1 >= 0;
+  f.own = sgn > 0 && own + 1 < sel3(ax, e0, e1, e2);
+  f.u = ux + e0 * (uy + e1 * uz);
+  f.ci = (ux + o0) + E.cext[0] * ((uy + o1) + E.cext[1] * (uz + o2));
+  f.gid = g0 + ux + g.s1 * uy + g.s2 * uz;
+  f.ax = ax;
+  f.sgn = sgn;
+  return f;
+}
+
 // Natural strides of global axis k in own-cell index space, closure space
 // and global cell space (k is a compile-time constant after unrolling).
 __device__ __forceinline__ int ustr(const EntDesc& E, int k) {
@@ -735,31 +810,21 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
   double kacc[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) kacc[i] = 0.0;
-  const int ncol = w.Ua * w.Ub;
-  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
-    const int col = i % ncol, k = i / ncol;
-    const int ja = col % w.Ua, jb = col / w.Ua;
-    int fm, um;
-    cell_masks(E, w, ja, jb, k, &fm, &um);
-    const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
+  const int nflux = owned_flux_count(E);
+  for (int item = threadIdx.x; item < nflux; item += BLOCK) {
+    const OwnedFlux f = owned_flux(E, a.g, w.g0, item);
+    if (!f.valid) continue;
+    const int ci = f.ci, cn = f.ci + f.sgn * cstr(E, f.ax);
+    const double T = harm(S.sig[ci], S.sig[cn]);
+    double dp[NCMAX];
 #pragma unroll
-    for (int dd = 0; dd < 6; ++dd) {
-      if (!((fm >> dd) & 1)) continue;
-      const bool own = (um >> dd) & 1;
-      if (!(dd & 1) && own) continue;  // counted from the lower own cell
-      const int sgn = (dd & 1) ? 1 : -1;
-      const int cn = ci + sgn * cstr(E, dd >> 1);
-      const double T = harm(S.sig[ci], S.sig[cn]);
-      double dp[NCMAX];
+    for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
+    int qq = 0;
 #pragma unroll
-      for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
-      int qq = 0;
+    for (int q = 0; q < NCMAX; ++q) {
+      const double tq = T * dp[q];
 #pragma unroll
-      for (int q = 0; q < NCMAX; ++q) {
-        const double tq = T * dp[q];
-#pragma unroll
-        for (int q2 = q; q2 < NCMAX; ++q2) kacc[qq++] += tq * dp[q2];
-      }
+      for (int q2 = q; q2 < NCMAX; ++q2) kacc[qq++] += tq * dp[q2];
     }
   }
   block_sum<NWAVE, NQ>(kacc, S.red);
@@ -1081,47 +1146,35 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
         ++qq;
       }
   }
-  const int ncol = w.Ua * w.Ub;
-  for (int i = threadIdx.x; i < ncol * w.L; i += BLOCK) {
-    const int col = i % ncol, k = i / ncol;
-    const int ja = col % w.Ua, jb = col / w.Ua;
-    int fm, um;
-    cell_masks(E, w, ja, jb, k, &fm, &um);
-    const int gid = w.g0 + ja * w.ga + jb * w.gb + k * w.gc;
-    const int u = ja * w.ua + jb * w.ub + k * w.uc;
-    const int ci = w.s0 + ja * w.sa + jb * w.sb + k * w.sc;
+  const int nflux = owned_flux_count(E);
+  for (int item = threadIdx.x; item < nflux; item += BLOCK) {
+    const OwnedFlux f = owned_flux(E, a.g, w.g0, item);
+    if (!f.valid) continue;
+    const int ci = f.ci, u = f.u, gid = f.gid;
+    const int cn = ci + f.sgn * cstr(E, f.ax);
+    const int un = u + f.sgn * ustr(E, f.ax);
+    const int gn = gid + f.sgn * gstr(a.g, f.ax);
+    double dp[NCMAX];
 #pragma unroll
-    for (int dd = 0; dd < 6; ++dd) {
-      if (!((fm >> dd) & 1)) continue;
-      const bool own = (um >> dd) & 1;
-      if (!(dd & 1) && own) continue;
-      const int sgn = (dd & 1) ? 1 : -1;
-      const int un = u + sgn * ustr(E, dd >> 1);
-      const int gn = gid + sgn * gstr(a.g, dd >> 1);
-      const int cn = ci + sgn * cstr(E, dd >> 1);
-      double dp[NCMAX];
+    for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
+    double wv = 0.0;
+    int qq = 0;
 #pragma unroll
-      for (int q = 0; q < NCMAX; ++q) dp[q] = q < nc ? S.phi[q * ncl + ci] - S.phi[q * ncl + cn] : 0.0;
-      double wv = 0.0;
-      int qq = 0;
+    for (int q = 0; q < NCMAX; ++q) {
+      double mq = 0.0;
+#pragma unroll
+      for (int q2 = q; q2 < NCMAX; ++q2) mq += mh[qq++] * dp[q2];
+      wv -= dp[q] * mq;
+    }
+    if (a.solve_adj) {
 #pragma unroll
       for (int q = 0; q < NCMAX; ++q) {
-        double mq = 0.0;
-#pragma unroll
-        for (int q2 = q; q2 < NCMAX; ++q2) mq += mh[qq++] * dp[q2];
-        wv -= dp[q] * mq;
+        if (q >= nc || S.wit[q] == 0) continue;
+        const double mun = f.own ? mus[q * a.nu_cap + un] : 0.0;
+        wv -= (mus[q * a.nu_cap + u] - mun) * dp[q];
       }
-      if (a.solve_adj) {
-#pragma unroll
-        for (int q = 0; q < NCMAX; ++q) {
-          if (q >= nc || S.wit[q] == 0) continue;
-          const double mun = own ? mus[q * a.nu_cap + un] : 0.0;
-          wv -= (mus[q * a.nu_cap + u] - mun) * dp[q];
-        }
-      }
-      const int ax = dd >> 1;
-      a.W[ax * N + ((dd & 1) ? gid : gn)] = wv;
     }
+    a.W[f.ax * N + (f.sgn > 0 ? gid : gn)] = wv;
   }
 }
 
