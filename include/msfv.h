@@ -93,7 +93,7 @@ typedef struct {
  *                         tables do not fit in on-chip memory.
  *   MSFV_COARSE_JACOBI  : M^-1 = D^-1.
  *   MSFV_COARSE_MULTI   : M^-1 = D^-1 with the multi-launch solver that
- *                         grids of more than 16384 vertices always use (all
+ *                         grids of more than 8192 vertices always use (all
  *                         right-hand sides per launch; the call returns when
  *                         the solve has finished).                         */
 enum { MSFV_COARSE_TWOLEVEL = 0, MSFV_COARSE_JACOBI = 1, MSFV_COARSE_MULTI = 2 };
@@ -123,7 +123,7 @@ typedef struct {
  * structure of S_k and A_k) and allocates its device state.  hip_stream is a
  * hipStream_t (NULL = default stream).  Unsupported geometry returns
  * MSFV_EINVAL: r outside [3, 16], n < 2 on an axis, more than 2^21 coarse
- * vertices or 2^31 cells.  Coarse grids of more than 16384 vertices are
+ * vertices or 2^31 cells.  Coarse grids of more than 8192 vertices are
  * solved by a multi-launch Jacobi-PCG whose forward and J^T v calls return
  * only when their coarse solves have finished (the host polls stop flags). */
 msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem** out);

@@ -1088,11 +1088,45 @@ msfv_status batch_run(msfv_batch* b, const double* const* m, const double* const
   const int ns = std::min<int>(b->streams, int(b->pool.size()));
   HIP_OK(hipEventRecord(b->fork, b->main));
   for (int k = 0; k < ns; ++k) HIP_OK(hipStreamWaitEvent(b->pool[k], b->fork, 0));
+  // Problems on the multi-launch coarse solver poll its stop flags from the
+  // host, which would hold up the issue of every other problem.  With more
+  // than one stream they get streams of their own, each driven by a host
+  // thread; the other problems are issued round-robin on the remaining
+  // streams by this thread.  Either list keeps the largest-first order.
+  std::vector<int> polled, plain;
   for (int q = 0; q < n; ++q) {
     const int i = b->order[q];
-    msfv_status st = batch_one(b, i, m[i], v[i], d_out[i], g_out[i], b->pool[q % ns]);
-    if (st != MSFV_OK) return st;
+    (ns > 1 && coarse_multi(b->probs[i]) ? polled : plain).push_back(i);
   }
+  const int nw = polled.empty() ? 0 : std::min<int>(int(polled.size()), std::max(1, ns / 2));
+  std::vector<msfv_status> wst(nw, MSFV_OK);
+  std::vector<std::string> werr(nw);
+  std::vector<std::thread> workers;
+  int device = 0;
+  if (nw > 0) HIP_OK(hipGetDevice(&device));
+  for (int w = 0; w < nw; ++w)
+    workers.emplace_back([&, w]() {
+      (void)hipSetDevice(device);  // the caller's device, current in this thread too
+      for (size_t k = w; k < polled.size(); k += nw) {
+        const int i = polled[k];
+        const msfv_status st = batch_one(b, i, m[i], v[i], d_out[i], g_out[i], b->pool[w]);
+        if (st != MSFV_OK) {
+          wst[w] = st;
+          werr[w] = msfv_last_error();
+          return;
+        }
+      }
+    });
+  msfv_status st = MSFV_OK;
+  const int nplain = ns - nw;
+  for (size_t k = 0; k < plain.size() && st == MSFV_OK; ++k) {
+    const int i = plain[k];
+    st = batch_one(b, i, m[i], v[i], d_out[i], g_out[i], b->pool[nw + int(k % nplain)]);
+  }
+  for (auto& t : workers) t.join();
+  if (st != MSFV_OK) return st;
+  for (int w = 0; w < nw; ++w)
+    if (wst[w] != MSFV_OK) return fail(wst[w], werr[w]);
   for (int k = 0; k < ns; ++k) {
     HIP_OK(hipEventRecord(b->done[k], b->pool[k]));
     HIP_OK(hipStreamWaitEvent(b->main, b->done[k], 0));

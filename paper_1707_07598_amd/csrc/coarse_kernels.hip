@@ -651,7 +651,9 @@ bool coarse_is_large(const int ncv[3]) {
   const int nc = ncv[0] * ncv[1] * ncv[2];
   const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
   const int ldk = coarse_ldk(nc);
-  return nc > 16 * kBlock || pcg_lds_bytes(ldk, pad, 0, qm_rows(ldk, ncv[0])) > 160 * 1024;
+  // more than 8 rows a thread spill in the single-workgroup kernel, which
+  // then runs slower than the multi-launch solver (measured 2.8x at 21^3)
+  return nc > 8 * kBlock || pcg_lds_bytes(ldk, pad, 0, qm_rows(ldk, ncv[0])) > 160 * 1024;
 }
 
 size_t coarse_large_workspace(const int ncv[3], int ns) {

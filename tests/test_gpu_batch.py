@@ -12,11 +12,14 @@ from oracle import reduced as R
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [((13, 11, 9), (4, 4, 4), 3),
-          ((36, 20, 19), (16, 8, 6), 2),    # r = 16 along x: the generic local kernels
-          ((32, 32), (4, 4), 2),            # 2-D
-          ((17, 9, 12), (8, 3, 4), 5),
-          ((24, 22, 20), (8, 8, 8), 1)]
+# (n, r, sources, coarse solver); the multi-launch coarse solver polls from
+# the host, so with several streams the batch drives those problems from
+# worker threads
+SHAPES = [((13, 11, 9), (4, 4, 4), 3, "twolevel"),
+          ((36, 20, 19), (16, 8, 6), 2, "twolevel"),    # r = 16 along x: the generic local kernels
+          ((32, 32), (4, 4), 2, "multi"),               # 2-D
+          ((17, 9, 12), (8, 3, 4), 5, "multi"),
+          ((24, 22, 20), (8, 8, 8), 1, "twolevel")]
 
 
 def _rel(a, b):
@@ -29,9 +32,9 @@ def batch_setup():
     import torch
     import paper_1707_07598_amd as msfv
     insts, probs, ms, vs = [], [], [], []
-    for k, (n, r, ns) in enumerate(SHAPES):
+    for k, (n, r, ns, pc) in enumerate(SHAPES):
         inst = W.small_instance(n, r, seed=40 + k, ns=ns, nr=6)
-        p = msfv.Problem(n, r, "reduced")
+        p = msfv.Problem(n, r, "reduced", coarse_precond=pc)
         p.set_sources(inst.sources)
         p.set_receivers(inst.receivers)
         insts.append(inst)

@@ -2,7 +2,7 @@
 
 * 64^3, r = 8, 16 surface dipoles, 256 receivers: D, t and the gradient
   element-wise against the oracle (same bars as the small cases).
-* a grid of more than 16384 coarse vertices (132 x 132 x 68, r = 4: 33 x 33
+* a grid of more than 8192 coarse vertices (132 x 132 x 68, r = 4: 33 x 33
   x 17), which takes the multi-launch coarse solver: pinned coarse residual,
   Galerkin invariants and a finite-difference directional derivative.
 * 128^3, r = 8, 32 surface dipoles, 1024 receivers, in the launch
