@@ -404,8 +404,8 @@ hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned 
   const msfv::Plan& P = p->plan;
   if (coarse_multi(p))
     return msfv::launch_coarse_pcg_large(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
-                                         p->cfg.coarse_maxit, p->d_cg_ws.ptr, p->h_flags,
-                                         p->d_status.ptr, work, s);
+                                         p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
+                                         p->d_cg_ws.ptr, p->h_flags, p->d_status.ptr, work, s);
   return msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
                                  p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
                                  p->d_status.ptr, work, s);
@@ -751,8 +751,8 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     HIP_OR_CLEAN(p->d_kdia.alloc(size_t(27) * ldk));
   }
   HIP_OR_CLEAN(hipMemsetAsync(p->d_kdia.ptr, 0, p->d_kdia.bytes(), s));
-  if (p->cfg.coarse_precond == MSFV_COARSE_TWOLEVEL && !msfv::coarse_is_large(P.ncv)) {
-    p->defl = msfv::coarse_defl_plan(P.ncv);
+  if (p->cfg.coarse_precond == MSFV_COARSE_TWOLEVEL) {
+    p->defl = msfv::coarse_is_large(P.ncv) ? msfv::coarse_defl_plan_large(P.ncv) : msfv::coarse_defl_plan(P.ncv);
     if (p->defl.ok) {
       HIP_OR_CLEAN(p->d_einv.alloc(size_t(p->defl.na) * p->defl.na));
       p->defl.einv = p->d_einv.ptr;

@@ -442,8 +442,11 @@ struct CgmState {
   double* r;      // ns * nc
   double* p;      // ns * nc
   double* q;      // ns * nc
-  double* part;   // 3 * ns * ntile: p.q, r.z, r.r
+  double* part;   // 3 * ns * ntile: p.q, r.D^-1 r, r.r
   double* scal;   // per source: rz[2], bb
+  double* s;      // two-level: per source 64 aggregate sums Z^T r
+  double* y;      // two-level: per source E^-1 s (64)
+  double* sy;     // two-level: per source s.y
   int* flag;      // per source: done[2], unused
 };
 
@@ -506,10 +509,10 @@ __global__ __launch_bounds__(kMT) void k_cgm_init(const double* __restrict__ kdi
 }
 
 // scalars of the initial residual (one thread per source)
-__global__ void k_cgm_start(int ns, int ntile, CgmState S) {
+__global__ void k_cgm_start(int ns, int ntile, int defl, CgmState S) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ns) return;
-  const double rz = sum_parts_serial(S.part + (size_t(1) * ns + j) * ntile, ntile);
+  const double rz = sum_parts_serial(S.part + (size_t(1) * ns + j) * ntile, ntile) + (defl ? S.sy[j] : 0.0);
   const double bb = sum_parts_serial(S.part + (size_t(2) * ns + j) * ntile, ntile);
   S.scal[3 * j + 0] = rz;
   S.scal[3 * j + 1] = rz;
@@ -518,6 +521,47 @@ __global__ void k_cgm_start(int ns, int ntile, CgmState S) {
   S.flag[3 * j + 0] = done;
   S.flag[3 * j + 1] = done;
   S.flag[3 * j + 2] = 0;
+}
+
+// Two-level correction of the multi-launch solver, z = D^-1 r + Z E^-1 Z^T r:
+// s = Z^T r by one workgroup per (aggregate, source), striding over the
+// aggregate's vertex list in a fixed order; then y = E^-1 s and s.y by one
+// wave per source (r.z = r.D^-1 r + s.y).  Sources already stopped are
+// skipped when live_only is set.
+__global__ __launch_bounds__(kMT) void k_cgm_aggsum(int nc, int ns, int par, int live_only, CoarseDefl d,
+                                                    CgmState S) {
+  __shared__ double red[kMT / kWave];
+  const int a = blockIdx.x, j = blockIdx.y;
+  if (live_only && S.flag[3 * j + par]) return;  // uniform over the workgroup
+  const int* rows = d.arows + d.na + 1;
+  const double* rj = S.r + size_t(j) * nc;
+  double t = 0.0;
+  for (int k = d.arows[a] + threadIdx.x; k < d.arows[a + 1]; k += kMT) t += rj[rows[k]];
+  t = tile_sum<kMT / kWave>(t, red);
+  if (threadIdx.x == 0) S.s[size_t(j) * 64 + a] = t;
+}
+
+__global__ __launch_bounds__(kWave) void k_cgm_ysolve(int ns, int par, int live_only, CoarseDefl d,
+                                                      CgmState S) {
+  const int j = blockIdx.x, t = threadIdx.x;
+  if (live_only && S.flag[3 * j + par]) return;
+  const double* sj = S.s + size_t(j) * 64;
+  double y = 0.0;
+  if (t < d.na)
+    for (int c = 0; c < d.na; ++c) y += d.einv[t * d.na + c] * sj[c];
+  if (t < d.na) S.y[size_t(j) * 64 + t] = y;
+  const double sy = wsum(t < d.na ? sj[t] * y : 0.0);
+  if (t == 0) S.sy[j] = sy;
+}
+
+// p += Z y after the initial residual (p = D^-1 r from the init kernel)
+__global__ __launch_bounds__(kMT) void k_cgm_pcorr(const double* __restrict__ kdia, int ldk, int ncx, int ncy,
+                                                   int nc, CoarseDefl d, CgmState S) {
+  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  if (i >= nc || i == 0) return;
+  if (!(kdia[13 * size_t(ldk) + i] > 0.0)) return;
+  const int a = agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy));
+  S.p[size_t(j) * nc + i] += S.y[size_t(j) * 64 + a];
 }
 
 __global__ __launch_bounds__(kMT) void k_cgm_spmv(const double* __restrict__ kdia, int ldk, int ncx,
@@ -586,10 +630,10 @@ __global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ k
 }
 
 // it: number of this iteration (1-based, the same for every source)
-__global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ kdia, int ldk, int nc,
-                                                     int ns, int ntile, int par, int it, double tol2,
-                                                     int maxit, CgmState S, int* status,
-                                                     unsigned long long* work) {
+__global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ kdia, int ldk, int ncx,
+                                                     int ncy, int nc, int ns, int ntile, int par, int it,
+                                                     double tol2, int maxit, int defl, CoarseDefl d,
+                                                     CgmState S, int* status, unsigned long long* work) {
   __shared__ double slot;
   const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
   const int nxt = par ^ 1;
@@ -600,7 +644,7 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
     }
     return;
   }
-  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile, &slot);
+  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile, &slot) + (defl ? S.sy[j] : 0.0);
   const double rr = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile, &slot);
   const bool conv = rr <= tol2 * S.scal[3 * j + 2];
   const bool bad = rr != rr || (!conv && it >= maxit);
@@ -620,7 +664,9 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
   const size_t o = size_t(j) * nc + i;
   const double dg = kdia[13 * size_t(ldk) + i];
   const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
-  S.p[o] = S.r[o] * dinv + beta * S.p[o];
+  double z = S.r[o] * dinv;
+  if (defl && dinv != 0.0) z += S.y[size_t(j) * 64 + agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy))];
+  S.p[o] = z + beta * S.p[o];
 }
 
 constexpr int kBlock = 1024;
@@ -659,12 +705,13 @@ bool coarse_is_large(const int ncv[3]) {
 size_t coarse_large_workspace(const int ncv[3], int ns) {
   const size_t nc = size_t(ncv[0]) * ncv[1] * ncv[2];
   const size_t ntile = (nc + kMT - 1) / kMT;
-  return (3 * nc * ns + 3 * ntile * ns + 3 * size_t(ns)) * sizeof(double) + 3 * size_t(ns) * sizeof(int);
+  return (3 * nc * ns + 3 * ntile * ns + 3 * size_t(ns) + 129 * size_t(ns)) * sizeof(double) +
+         3 * size_t(ns) * sizeof(int);
 }
 
 hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                                   int ns, double rtol, int maxit, void* workspace, int* host_flags,
-                                   int* status, unsigned long long* work, hipStream_t s) {
+                                   int ns, double rtol, int maxit, const CoarseDefl* defl, void* workspace,
+                                   int* host_flags, int* status, unsigned long long* work, hipStream_t s) {
   if (ns == 0) return hipSuccess;
   const int nc = ncv[0] * ncv[1] * ncv[2];
   const int ldk = coarse_ldk(nc);
@@ -676,10 +723,20 @@ hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const d
   S.q = S.p + size_t(ns) * nc;
   S.part = S.q + size_t(ns) * nc;
   S.scal = S.part + size_t(3) * ntile * ns;
-  S.flag = reinterpret_cast<int*>(S.scal + size_t(3) * ns);
-  const dim3 gt(ntile, ns), gs(ntile, (ns + kMG - 1) / kMG);
+  S.s = S.scal + size_t(3) * ns;
+  S.y = S.s + size_t(64) * ns;
+  S.sy = S.y + size_t(64) * ns;
+  S.flag = reinterpret_cast<int*>(S.sy + size_t(ns));
+  const bool two = defl && defl->ok && defl->einv && defl->arows && defl->na <= 64;
+  const CoarseDefl d = two ? *defl : CoarseDefl();
+  const dim3 gt(ntile, ns), gs(ntile, (ns + kMG - 1) / kMG), ga(two ? d.na : 1, ns);
   hipLaunchKernelGGL(k_cgm_init, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, rhs, x, S);
-  hipLaunchKernelGGL(k_cgm_start, dim3((ns + 255) / 256), dim3(256), 0, s, ns, ntile, S);
+  if (two) {
+    hipLaunchKernelGGL(k_cgm_aggsum, ga, dim3(kMT), 0, s, nc, ns, 0, 0, d, S);
+    hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kWave), 0, s, ns, 0, 0, d, S);
+    hipLaunchKernelGGL(k_cgm_pcorr, gt, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], nc, d, S);
+  }
+  hipLaunchKernelGGL(k_cgm_start, dim3((ns + 255) / 256), dim3(256), 0, s, ns, ntile, two ? 1 : 0, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double tol2 = rtol * rtol;
@@ -692,8 +749,12 @@ hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const d
       hipLaunchKernelGGL(k_cgm_spmv, gs, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], ncv[2], ns, ntile,
                          par, S);
       hipLaunchKernelGGL(k_cgm_update, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, par, x, S);
-      hipLaunchKernelGGL(k_cgm_pupdate, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, par, it + 1,
-                         tol2, maxit, S, status, work);
+      if (two) {
+        hipLaunchKernelGGL(k_cgm_aggsum, ga, dim3(kMT), 0, s, nc, ns, par, 1, d, S);
+        hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kWave), 0, s, ns, par, 1, d, S);
+      }
+      hipLaunchKernelGGL(k_cgm_pupdate, gt, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], nc, ns, ntile, par,
+                         it + 1, tol2, maxit, two ? 1 : 0, d, S, status, work);
       par ^= 1;
     }
     e = hipGetLastError();
@@ -707,6 +768,12 @@ hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const d
     if (all) break;
   }
   return hipSuccess;
+}
+
+CoarseDefl coarse_defl_plan_large(const int ncv[3]) {
+  CoarseDefl d = coarse_defl_plan(ncv);
+  d.ok = d.na >= 2 && setup_lds_bytes(d.na) <= 160 * 1024;
+  return d;
 }
 
 CoarseDefl coarse_defl_plan(const int ncv[3]) {

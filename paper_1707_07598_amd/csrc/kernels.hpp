@@ -97,6 +97,8 @@ struct CoarseDefl {
   const int* arows = nullptr;   // device: aggregate offsets (na + 1), then the vertices by aggregate
 };
 CoarseDefl coarse_defl_plan(const int ncv[3]);
+// the same boxes for the multi-launch solver (E^-1 in LDS only for the setup)
+CoarseDefl coarse_defl_plan_large(const int ncv[3]);
 // Host table for CoarseDefl::arows: offsets of each aggregate's vertices
 // (na + 1 entries), then the vertex ids aggregate by aggregate, x fastest
 // within a box.
@@ -105,16 +107,17 @@ std::vector<int> coarse_defl_rows(const CoarseDefl& d, const int ncv[3]);
 // non-converged coarse solve in status.
 hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const CoarseDefl& d,
                                     double* einv, int* status, hipStream_t s);
-// Coarse systems too large for one workgroup's LDS take the multi-launch
-// solver: Jacobi-PCG over all columns, three launches per iteration, and the
-// host polls the stop flags every few iterations (so the call blocks until
-// the solve ends).  workspace: coarse_large_workspace bytes of device memory;
-// host_flags: 3*ns ints of pinned host memory.
+// Coarse systems too large for one workgroup take the multi-launch solver:
+// PCG over all columns, three launches per iteration (five with the
+// two-level correction, when defl is given), and the host polls the stop
+// flags every few iterations (so the call blocks until the solve ends).
+// workspace: coarse_large_workspace bytes of device memory; host_flags: 3*ns
+// ints of pinned host memory.
 bool coarse_is_large(const int ncv[3]);
 size_t coarse_large_workspace(const int ncv[3], int ns);
 hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const double* rhs, double* x,
-                                   int ns, double rtol, int maxit, void* workspace, int* host_flags,
-                                   int* status, unsigned long long* work, hipStream_t s);
+                                   int ns, double rtol, int maxit, const CoarseDefl* defl, void* workspace,
+                                   int* host_flags, int* status, unsigned long long* work, hipStream_t s);
 // PCG on A_k with vertex 0 fixed, one workgroup per column of rhs; Jacobi
 // preconditioned, plus the aggregate correction when defl is given.
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,

@@ -132,11 +132,13 @@ def test_small_2d_workload_parity():
                                     ((172, 160), (4, 4), 2),          # 2-D 43 x 40: rows strided (odd Ncx)
                                     ((64, 64), (3, 4), 4),            # 2-D, 22 x 16
                                     ((128, 64), (4, 4), 3),           # 2-D 32 x 16, odd source count
-                                    ((32, 32, 24), (4, 4, 4), 5)])    # 8 x 8 x 6
+                                    ((32, 32, 24), (4, 4, 4), 5),     # 8 x 8 x 6
+                                    ((516, 256), (4, 4), 3)])         # 2-D 129 x 64 > 8192: multi-launch
 def test_coarse_preconditioners_parity(n, r, ns):
     """The coarse solvers (two-level aggregate correction, plain Jacobi, and
-    the multi-launch Jacobi solver of large grids) give D, t and the gradient
-    of the oracle, and agree with each other."""
+    the multi-launch Jacobi solver of large grids; above 8192 vertices all
+    three run multi-launch, two-level with the aggregate correction) give D,
+    t and the gradient of the oracle, and agree with each other."""
     torch = _torch()
     inst = W.small_instance(n, r, seed=17, ns=ns, nr=9)
     g = Geometry(n, r)
