@@ -85,13 +85,16 @@ __device__ __forceinline__ double p_lookup(const int* prow, const int* pcol, con
   return v;
 }
 
+// Per own cell the thread keeps only its geometry and diagonal; the
+// transmissibilities live in LDS (tp: the +k flux of every own cell, zero
+// where there is none), so a thread's state stays in registers.
 struct CellGeo {
   int u;      // own-cell index, -1 for an unused slot
   int gid;    // global cell id
+  int ci;     // closure index
   int gc[3];  // global coordinates
   int fmask;  // bit d = 2k+plus: a flux of the reduced operator exists in direction d
   int umask;  // bit d: that neighbour is an own cell (else a Dirichlet cell)
-  double T[6];
   double diag;
   double dinv;
 };
@@ -104,9 +107,14 @@ __device__ __forceinline__ int ustride_of(const EntDesc& E, int k) {
   return k == 0 ? 1 : (k == 1 ? E.uext[0] : E.uext[0] * E.uext[1]);
 }
 
-// Neighbour geometry of own cell u from the closure conductivities in LDS.
+__device__ __forceinline__ int cstride_of(const EntDesc& E, int k) {
+  return k == 0 ? 1 : (k == 1 ? E.cext[0] : E.cext[0] * E.cext[1]);
+}
+
+// Neighbour geometry of own cell u from the closure conductivities in LDS;
+// writes the cell's +k transmissibilities to tp[k * nu + u].
 __device__ void cell_setup(const EntDesc& E, const GridInfo& g, const double* sig, int u,
-                           CellGeo& c) {
+                           CellGeo& c, double* tp) {
   c.u = u;
   const int ux = u % E.uext[0];
   const int t = u / E.uext[0];
@@ -120,6 +128,7 @@ __device__ void cell_setup(const EntDesc& E, const GridInfo& g, const double* si
   const int cs[3] = {1, E.cext[0], E.cext[0] * E.cext[1]};
   const int uc[3] = {ux, uy, uz};
   const int lc = l[0] + cs[1] * l[1] + cs[2] * l[2];
+  c.ci = lc;
   const double s0 = sig[lc];
   double diag = 0.0;
   c.fmask = 0;
@@ -129,13 +138,13 @@ __device__ void cell_setup(const EntDesc& E, const GridInfo& g, const double* si
 #pragma unroll
     for (int pl = 0; pl < 2; ++pl) {
       const int d = 2 * k + pl;
-      c.T[d] = 0.0;
+      if (pl) tp[k * E.nu + u] = 0.0;
       if (!((E.open_mask >> k) & 1)) continue;
       const int step = pl ? 1 : -1;
       const int lk = l[k] + step;
       if (lk < 0 || lk >= E.cext[k]) continue;  // outside the closure = outside the domain
       const double tt = harm(s0, sig[lc + step * cs[k]]);
-      c.T[d] = tt;
+      if (pl) tp[k * E.nu + u] = tt;
       diag += tt;
       c.fmask |= 1 << d;
       const int uk = uc[k] + step;
@@ -144,6 +153,19 @@ __device__ void cell_setup(const EntDesc& E, const GridInfo& g, const double* si
   }
   c.diag = diag;
   c.dinv = diag > 0.0 ? 1.0 / diag : 0.0;
+}
+
+// Transmissibility of the flux of cell c in direction d (which must exist):
+// the cell's own +k entry, the -k neighbour's +k entry, or, towards a
+// Dirichlet cell on the lower side, the harmonic mean from the closure
+// conductivities.  The -k entry of an own neighbour is written by another
+// thread: read it only after the workgroup barrier that follows the setup.
+__device__ __forceinline__ double cell_T(const EntDesc& E, const CellGeo& c, int d, const double* sig,
+                                         const double* tp) {
+  const int k = d >> 1;
+  if (d & 1) return tp[k * E.nu + c.u];
+  if ((c.umask >> d) & 1) return tp[k * E.nu + c.u - ustride_of(E, k)];
+  return harm(sig[c.ci], sig[c.ci - cstride_of(E, k)]);
 }
 
 __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[3], int ci) {
@@ -163,7 +185,7 @@ __device__ __forceinline__ double lagrange_value(const EntDesc& E, const int gc[
 // live in LDS (pb[c*nu + u]); x, r and p for the thread's own cells live in
 // registers.  Stops when ||r_c|| <= rtol ||b_c|| for every column.
 template <int BLOCK, int CPT, int NCP>
-__device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], int ncp,
+__device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], const double* tp, int ncp,
                          const double (&b)[CPT][NCP], double (&x)[CPT][NCP], double* pb,
                          double* redA, double* redB, double tol2, int maxit, bool* ok) {
   constexpr int NW = BLOCK / kWave;
@@ -218,7 +240,7 @@ __device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], int ncp,
         if (!((cg[j].umask >> d) & 1)) continue;
         const int k = d >> 1;
         const int nb = cg[j].u + ((d & 1) ? ustride_of(E, k) : -ustride_of(E, k));
-        const double tt = cg[j].T[d];
+        const double tt = (d & 1) ? tp[k * nu + cg[j].u] : tp[k * nu + nb];
 #pragma unroll
         for (int c = 0; c < NCP; ++c)
           if (c < ncp) ap[j][c] -= tt * pb[c * nu + nb];
@@ -302,11 +324,12 @@ template <int BLOCK, int CPT, int NCP>
 __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
-  const EntDesc E = a.ents[blockIdx.x];
+  const EntDesc& E = a.ents[blockIdx.x];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
   double* redA = pb + NCP * a.nu_cap;
   double* redB = redA + NW * 40;
+  double* tp = redB + NW * 40;  // 3 * nu_cap
   load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
   __syncthreads();
   CellGeo cg[CPT];
@@ -314,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   for (int j = 0; j < CPT; ++j) {
     const int u = threadIdx.x + j * BLOCK;
     if (u < E.nu)
-      cell_setup(E, a.g, sig, u, cg[j]);
+      cell_setup(E, a.g, sig, u, cg[j], tp);
     else
       cg[j].u = -1;
   }
@@ -345,12 +368,12 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
           const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
 #pragma unroll
           for (int c = 0; c < NCP; ++c)
-            if (c < ncp) b[j][c] += cg[j].T[d] * p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c0 + c]);
+            if (c < ncp) b[j][c] += cell_T(E, cg[j], d, sig, tp) * p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c0 + c]);
         }
       }
       __syncthreads();  // previous pass finished with the LDS buffers
       bool ok = true;
-      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
       work += (unsigned long long)it * E.nu * ncp;
@@ -403,7 +426,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
         const double pn = own ? a.pval[nbase + c] : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]);
         dp[c] = pu[c] - pn;
       }
-      const double tt = cg[j].T[d];
+      const double tt = cell_T(E, cg[j], d, sig, tp);
       int q = 0;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
@@ -436,13 +459,14 @@ template <int BLOCK, int CPT, int NCP>
 __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
-  const EntDesc E = a.ents[blockIdx.x];
+  const EntDesc& E = a.ents[blockIdx.x];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
   double* redA = pb + NCP * a.nu_cap;
   double* redB = redA + NW * 40;
   double* Mm = redB + NW * 40;  // 64
   double* Sm = Mm + 64;         // 64
+  double* tp = Sm + 64;         // 3 * nu_cap
   load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
   const int nc = E.nc;
   if (threadIdx.x < nc * nc) {
@@ -462,7 +486,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
   for (int j = 0; j < CPT; ++j) {
     const int u = threadIdx.x + j * BLOCK;
     if (u < E.nu)
-      cell_setup(E, a.g, sig, u, cg[j]);
+      cell_setup(E, a.g, sig, u, cg[j], tp);
     else
       cg[j].u = -1;
   }
@@ -538,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
         for (int c = 0; c < NCP; ++c) b[j][c] = (c < ncp) ? zh[j][c0 + c] : 0.0;
       __syncthreads();
       bool ok = true;
-      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
       work += (unsigned long long)it * E.nu * ncp;
@@ -586,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
             int gc2[3] = {cg[j].gc[0], cg[j].gc[1], cg[j].gc[2]};
             gc2[k] += (d & 1) ? 1 : -1;
             const int ut = (gc2[0] - R.ulo[0]) + R.uext[0] * ((gc2[1] - R.ulo[1]) + R.uext[1] * (gc2[2] - R.ulo[2]));
-            const double tt = cg[j].T[d];
+            const double tt = cell_T(E, cg[j], d, sig, tp);
 #pragma unroll
             for (int c = 0; c < NCP; ++c) {
               if (c >= ncp) continue;
@@ -1090,7 +1114,7 @@ __global__ void k_residual(const double* D, const double* dobs, double* v, long 
 template <int BLOCK, int CPT, int NCP>
 size_t local_lds_bytes(const LocalParams& p, bool adj) {
   const int nw = BLOCK / kWave;
-  size_t d = size_t(p.sig_cap) + size_t(NCP) * p.nu_cap + 2 * nw * 40 + (adj ? 128 : 0);
+  size_t d = size_t(p.sig_cap) + size_t(NCP) * p.nu_cap + 2 * nw * 40 + (adj ? 128 : 0) + size_t(3) * p.nu_cap;
   return d * sizeof(double);
 }
 
@@ -1120,7 +1144,7 @@ hipError_t launch_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (nu <= 384) return launch_local_t<384, 1, 8>(p, adj, s);
   if (nu <= 512) return launch_local_t<512, 1, 8>(p, adj, s);
   if (nu <= 1024) return launch_local_t<1024, 1, 4>(p, adj, s);
-  if (nu <= 4096) return launch_local_t<512, 8, 2>(p, adj, s);
+  if (nu <= 4096) return launch_local_t<512, 8, 1>(p, adj, s);  // LDS: sigma, one direction, tp
   return hipErrorInvalidConfiguration;
 }
 
