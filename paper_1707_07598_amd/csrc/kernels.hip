@@ -548,7 +548,51 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
     }
   }
 
-  if (a.solve_adj) {
+  // An entity with no electrode loads and no pushes from above (dual blocks
+  // off the electrodes) has mu_c = 0 for every corner: the flux weights keep
+  // their quadratic part, and one sweep writes the y-part of every corner's
+  // pushes, without the corner passes.
+  const bool loaded = E.nslot > 0 || E.eptr1 > E.eptr0;
+  if (a.solve_adj && !loaded) {
+    if (a.push) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        if (cg[j].u < 0) continue;
+        const int base = a.prow[cg[j].gid];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          if (!((cg[j].fmask >> d) & 1) || ((cg[j].umask >> d) & 1)) continue;
+          const int te = E.side_ent[d];
+          if (te < 0) continue;
+          const int k = d >> 1;
+          const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+          double dp[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            dp[c] = c < nc ? a.pval[base + c] - p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]) : 0.0;
+          const EntDesc& R = a.recv[te];
+          int gc2[3] = {cg[j].gc[0], cg[j].gc[1], cg[j].gc[2]};
+          gc2[k] += (d & 1) ? 1 : -1;
+          const int ut = (gc2[0] - R.ulo[0]) + R.uext[0] * ((gc2[1] - R.ulo[1]) + R.uext[1] * (gc2[2] - R.ulo[2]));
+          const double tt = cell_T(E, cg[j], d, sig, tp);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if (c >= nc) continue;
+            int ct = -1;
+            for (int q = 0; q < R.nc; ++q)
+              if (R.vid[q] == E.vid[c]) ct = q;
+            if (ct < 0) continue;
+            double dy = 0.0;
+#pragma unroll
+            for (int c2 = 0; c2 < 8; ++c2)
+              if (c2 < nc) dy += Sm[c2 * nc + c] * dp[c2];
+            a.outbuf[R.inbase + (E.side_slot[d] * R.nc + ct) * R.nu + ut] = tt * dy;
+          }
+        }
+      }
+    }
+    if (threadIdx.x == 0 && a.ent_it) a.ent_it[blockIdx.x] = 0;
+  } else if (a.solve_adj) {
     const double tol2 = a.rtol * a.rtol;
     int itmax = 0;
     unsigned long long work = 0;
