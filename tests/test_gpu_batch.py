@@ -119,3 +119,39 @@ def test_batch_errors():
         msfv.Batch([p, p])
     assert e.value.status == _lib.MSFV_EINVAL
     p.close()
+
+
+def test_batch_error_from_a_polled_problem():
+    """A failing problem on the multi-launch coarse solver (driven from a
+    worker thread when there are several streams) surfaces at the batch sync;
+    the other problems' results are still those of their eager calls."""
+    import torch
+    import paper_1707_07598_amd as msfv
+    from paper_1707_07598_amd import _lib
+    specs = [((13, 11, 9), (4, 4, 4), 2, "twolevel", 1000),
+             ((32, 32), (4, 4), 2, "multi", 1),            # local solves capped: fails
+             ((17, 9, 12), (8, 3, 4), 3, "multi", 1000)]
+    probs, ms, vs = [], [], []
+    for k, (n, r, ns, pc, maxit) in enumerate(specs):
+        inst = W.small_instance(n, r, seed=60 + k, ns=ns, nr=4)
+        p = msfv.Problem(n, r, "reduced", coarse_precond=pc, local_maxit=maxit)
+        p.set_sources(inst.sources)
+        p.set_receivers(inst.receivers)
+        probs.append(p)
+        ms.append(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
+        vs.append(torch.tensor(np.random.default_rng(70 + k).standard_normal((ns, 4)), dtype=torch.float64,
+                               device="cuda"))
+    eager = {}
+    for k in (0, 2):
+        eager[k] = (probs[k].forward(ms[k]).clone(), probs[k].jtv(vs[k]).clone())
+    b = msfv.Batch(probs)
+    b.set_options(4, False)
+    D, g = b.forward_jtv(ms, vs, sync=False)
+    with pytest.raises(msfv.MsfvError) as e:
+        b.sync()
+    assert e.value.status == _lib.MSFV_ENOCONV
+    for k in (0, 2):
+        assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), k
+    b.close()
+    for p in probs:
+        p.close()
