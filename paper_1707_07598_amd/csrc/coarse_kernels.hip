@@ -107,72 +107,78 @@ __device__ __forceinline__ void aggregate_sums(const double* stage, const Coarse
 }
 
 // ---------------------------------------------------------------------------
-// E = Z^T A_k Z over the free vertices (vertex 0 excluded) and its inverse,
-// by one workgroup.  Assembly: 16 lanes per aggregate a; each lane walks its
-// share of the box's vertices and adds every stencil coefficient K_ij into
-// one of 27 accumulators, by the direction D from a to the aggregate of j
-// (each axis steps out of the box only from the box face on that side); the
-// 16-lane sums are E[a][a + D].  Inversion: Gauss-Jordan (E is SPD, so no
-// pivoting), lane = column, 16 waves sharing the rows, two barriers a step.
+// E = Z^T A_k Z over the free vertices (vertex 0 excluded), one wave per
+// aggregate a: each lane walks its share of the box's vertices and adds
+// every stencil coefficient K_ij into one of 27 accumulators, by the
+// direction D from a to the aggregate of j (each axis steps out of the box
+// only from the box face on that side); the wave sums are E[a][a + D], and
+// the wave writes row a of E (zeros elsewhere) to the global buffer e.
+__global__ __launch_bounds__(kWave) void k_coarse_defl_assemble(const double* __restrict__ kdia, int ldk,
+                                                                int ncx, int ncy, int ncz, CoarseDefl d,
+                                                                double* e) {
+  const int na = d.na;
+  const int a = blockIdx.x, l = threadIdx.x;
+  const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
+  const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
+  const int w = min(d.b[0], ncx - x0), h = min(d.b[1], ncy - y0), dd = min(d.b[2], ncz - z0);
+  const int cnt = w * h * dd;
+  double acc[27];
+#pragma unroll
+  for (int D = 0; D < 27; ++D) acc[D] = 0.0;
+  for (int k = l; k < cnt; k += kWave) {
+    const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
+    const int i = x + ncx * (y + ncy * z);
+    if (i == 0) continue;
+    const bool lo[3] = {x == x0, y == y0, z == z0};
+    const bool hi[3] = {x == x0 + w - 1, y == y0 + h - 1, z == z0 + dd - 1};
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+      if (i + ox + ncx * (oy + ncy * oz) == 0) continue;  // the fixed vertex
+      const double v = kdia[size_t(o) * ldk + i];
+      // aggregate step on each axis
+      const int sx = ox < 0 ? (lo[0] ? -1 : 0) : (ox > 0 ? (hi[0] ? 1 : 0) : 0);
+      const int sy = oy < 0 ? (lo[1] ? -1 : 0) : (oy > 0 ? (hi[1] ? 1 : 0) : 0);
+      const int sz = oz < 0 ? (lo[2] ? -1 : 0) : (oz > 0 ? (hi[2] ? 1 : 0) : 0);
+      // candidate directions of this offset: 0 or the offset's own step per axis
+#pragma unroll
+      for (int cz = 0; cz < (oz ? 2 : 1); ++cz)
+#pragma unroll
+        for (int cy = 0; cy < (oy ? 2 : 1); ++cy)
+#pragma unroll
+          for (int cx = 0; cx < (ox ? 2 : 1); ++cx) {
+            const int Dx = cx ? ox : 0, Dy = cy ? oy : 0, Dz = cz ? oz : 0;
+            const bool hit = sx == Dx && sy == Dy && sz == Dz;
+            acc[(Dx + 1) + 3 * (Dy + 1) + 9 * (Dz + 1)] += hit ? v : 0.0;
+          }
+    }
+  }
+#pragma unroll
+  for (int D = 0; D < 27; ++D) acc[D] = wsum(acc[D]);
+  // row a: lane b writes E[a][b] (and b + 64 ... for larger na)
+  for (int b = l; b < na; b += kWave) {
+    const int bx = b % d.na3[0], by = (b / d.na3[0]) % d.na3[1], bz = b / (d.na3[0] * d.na3[1]);
+    const int Dx = bx - ax, Dy = by - ay, Dz = bz - az;
+    double v = 0.0;
+#pragma unroll
+    for (int D = 0; D < 27; ++D)
+      if (Dx == D % 3 - 1 && Dy == (D / 3) % 3 - 1 && Dz == D / 9 - 1) v = acc[D];
+    e[size_t(a) * na + b] = v;
+  }
+}
+
+// The inverse of E (read from e, which may alias einv), by one workgroup:
+// Gauss-Jordan (E is SPD, so no pivoting), lane = column, 16 waves sharing
+// the rows, two barriers a step; the symmetric part is written to einv.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* __restrict__ kdia, int ldk,
-                                                             int ncx, int ncy, int ncz, CoarseDefl d,
+__global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* e, CoarseDefl d,
                                                              double* einv, int* status) {
   extern __shared__ double lds[];
   const int na = d.na;
   double* E = lds;  // na * na, row-major
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
-  for (int i = threadIdx.x; i < na * na; i += BLOCK) E[i] = 0.0;
-  __syncthreads();
-  const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
-  for (int a = grp; a < na; a += BLOCK / 16) {
-    const int ax = a % d.na3[0], ay = (a / d.na3[0]) % d.na3[1], az = a / (d.na3[0] * d.na3[1]);
-    const int x0 = ax * d.b[0], y0 = ay * d.b[1], z0 = az * d.b[2];
-    const int w = min(d.b[0], ncx - x0), h = min(d.b[1], ncy - y0), dd = min(d.b[2], ncz - z0);
-    const int cnt = w * h * dd;
-    double acc[27];
-#pragma unroll
-    for (int D = 0; D < 27; ++D) acc[D] = 0.0;
-    for (int k = l; k < cnt; k += 16) {
-      const int x = x0 + k % w, y = y0 + (k / w) % h, z = z0 + k / (w * h);
-      const int i = x + ncx * (y + ncy * z);
-      if (i == 0) continue;
-      const bool lo[3] = {x == x0, y == y0, z == z0};
-      const bool hi[3] = {x == x0 + w - 1, y == y0 + h - 1, z == z0 + dd - 1};
-#pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        if (i + ox + ncx * (oy + ncy * oz) == 0) continue;  // the fixed vertex
-        const double v = kdia[size_t(o) * ldk + i];
-        // aggregate step on each axis
-        const int sx = ox < 0 ? (lo[0] ? -1 : 0) : (ox > 0 ? (hi[0] ? 1 : 0) : 0);
-        const int sy = oy < 0 ? (lo[1] ? -1 : 0) : (oy > 0 ? (hi[1] ? 1 : 0) : 0);
-        const int sz = oz < 0 ? (lo[2] ? -1 : 0) : (oz > 0 ? (hi[2] ? 1 : 0) : 0);
-        // candidate directions of this offset: 0 or the offset's own step per axis
-#pragma unroll
-        for (int cz = 0; cz < (oz ? 2 : 1); ++cz)
-#pragma unroll
-          for (int cy = 0; cy < (oy ? 2 : 1); ++cy)
-#pragma unroll
-            for (int cx = 0; cx < (ox ? 2 : 1); ++cx) {
-              const int Dx = cx ? ox : 0, Dy = cy ? oy : 0, Dz = cz ? oz : 0;
-              const bool hit = sx == Dx && sy == Dy && sz == Dz;
-              acc[(Dx + 1) + 3 * (Dy + 1) + 9 * (Dz + 1)] += hit ? v : 0.0;
-            }
-      }
-    }
-#pragma unroll
-    for (int D = 0; D < 27; ++D) acc[D] = row16_sum(acc[D]);
-    if (l == 0) {
-#pragma unroll
-      for (int D = 0; D < 27; ++D) {
-        const int bx = ax + D % 3 - 1, by = ay + (D / 3) % 3 - 1, bz = az + D / 9 - 1;
-        if (bx >= 0 && bx < d.na3[0] && by >= 0 && by < d.na3[1] && bz >= 0 && bz < d.na3[2])
-          E[a * na + bx + d.na3[0] * (by + d.na3[1] * bz)] = acc[D];
-      }
-    }
-  }
+  for (int i = threadIdx.x; i < na * na; i += BLOCK) E[i] = e[i];
   __syncthreads();
   const int j = threadIdx.x % kWave, rg = threadIdx.x / kWave;
   constexpr int NRG = BLOCK / kWave;
@@ -823,8 +829,10 @@ hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const 
                                        int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(1), dim3(kBlock), lds, s, kdia, coarse_ldk(nc), ncv[0], ncv[1],
-                     ncv[2], d, einv, status);
+  // E assembled into einv by one wave an aggregate, then inverted in place
+  hipLaunchKernelGGL(k_coarse_defl_assemble, dim3(d.na), dim3(kWave), 0, s, kdia, coarse_ldk(nc), ncv[0],
+                     ncv[1], ncv[2], d, einv);
+  hipLaunchKernelGGL(kern, dim3(1), dim3(kBlock), lds, s, einv, d, einv, status);
   return hipGetLastError();
 }
 
