@@ -169,44 +169,45 @@ __global__ __launch_bounds__(kWave) void k_coarse_defl_assemble(const double* __
 
 // The inverse of E (read from e, which may alias einv), by one workgroup:
 // Gauss-Jordan (E is SPD, so no pivoting), lane = column, 16 waves sharing
-// the rows, two barriers a step; the symmetric part is written to einv.
+// the rows, one barrier a step; the symmetric part is written to einv.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* e, CoarseDefl d,
                                                              double* einv, int* status) {
   extern __shared__ double lds[];
   const int na = d.na;
-  double* E = lds;  // na * na, row-major
+  // two copies of E (row-major): step k reads one and writes the other, so a
+  // step needs one barrier
+  double* cur = lds;
+  double* nxt = lds + na * na;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
-  for (int i = threadIdx.x; i < na * na; i += BLOCK) E[i] = e[i];
+  for (int i = threadIdx.x; i < na * na; i += BLOCK) cur[i] = e[i];
   __syncthreads();
   const int j = threadIdx.x % kWave, rg = threadIdx.x / kWave;
   constexpr int NRG = BLOCK / kWave;
   for (int k = 0; k < na; ++k) {
-    const double piv = E[k * na + k];
+    const double piv = cur[k * na + k];
     const double inv = 1.0 / piv;
-    const double rk = j < na ? (j == k ? inv : E[k * na + j] * inv) : 0.0;
-    double f[64 / NRG];
-#pragma unroll
-    for (int t = 0; t < 64 / NRG; ++t) {
-      const int i = rg + t * NRG;
-      f[t] = i < na ? E[i * na + k] : 0.0;
-    }
+    const double rk = j < na ? (j == k ? inv : cur[k * na + j] * inv) : 0.0;
     if (threadIdx.x == 0 && !(piv > 0.0)) bad = 1;
-    __syncthreads();
     if (j < na) {
 #pragma unroll
       for (int t = 0; t < 64 / NRG; ++t) {
         const int i = rg + t * NRG;
         if (i >= na) continue;
+        const double f = cur[i * na + k];
         if (i == k)
-          E[i * na + j] = rk;
+          nxt[i * na + j] = rk;
         else
-          E[i * na + j] = j == k ? -f[t] * inv : E[i * na + j] - f[t] * rk;
+          nxt[i * na + j] = j == k ? -f * inv : cur[i * na + j] - f * rk;
       }
     }
     __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
   }
+  double* E = cur;
   if (threadIdx.x == 0 && bad) atomicAdd(status + kStCoarseNoconv, 1);
   // symmetric part (the exact inverse is symmetric)
   for (int t = threadIdx.x; t < na * na; t += BLOCK) {
@@ -688,7 +689,7 @@ size_t pcg_lds_bytes(int ldk, int pad, int na, int qm = 0) {
   return (pn + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128) * sizeof(double);
 }
 
-size_t setup_lds_bytes(int na) { return size_t(na) * na * sizeof(double); }
+size_t setup_lds_bytes(int na) { return 2 * size_t(na) * na * sizeof(double); }
 
 }  // namespace
 
