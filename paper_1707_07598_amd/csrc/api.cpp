@@ -349,7 +349,7 @@ msfv_status build_electrodes(msfv_problem* p) {
     HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, std::max(1, ns)) / sizeof(double) + 1));
     if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
     p->h_flags = nullptr;
-    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 3 * std::max(1, ns)));
+    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * std::max(1, ns)));
   }
   HIP_OK(hipStreamSynchronize(s));  // host vectors above are temporaries
   p->electrodes_ready = true;

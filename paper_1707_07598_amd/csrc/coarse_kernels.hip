@@ -445,6 +445,20 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 constexpr int kMT = 256;  // rows per tile (one per thread)
 constexpr int kMG = 8;    // sources per spmv workgroup
 
+// The per-row kernels run on a 1-D grid whose workgroups go round-robin over
+// the eight XCDs (linear id mod 8).  Linear id L maps to (tile, column) so
+// that XCD x takes the contiguous tiles [x*tpx, (x+1)*tpx) of every column:
+// a tile's rows, their stencil halo and their coefficients then stay in one
+// XCD's L2 across the columns.  Returns false for the ids past the last tile.
+__device__ __forceinline__ bool xcd_tile(int ntile, int& tile, int& col) {
+  const int tpx = (ntile + 7) / 8, L = blockIdx.x;
+  const int x = L % 8, k = L / 8;
+  tile = x * tpx + k % tpx;
+  col = k / tpx;
+  return tile < ntile;
+}
+inline unsigned xcd_grid(int ntile, int ncol) { return 8u * unsigned((ntile + 7) / 8) * unsigned(ncol); }
+
 struct CgmState {
   double* r;      // ns * nc
   double* p;      // ns * nc
@@ -484,6 +498,28 @@ __device__ __forceinline__ double sum_parts(const double* part, int ntile, doubl
   return v;
 }
 
+// Two such sums at once (one pass, one pair of barriers).
+__device__ __forceinline__ void sum_parts2(const double* pa, const double* pb, int ntile, double* slot,
+                                           double& a, double& b) {
+  if (threadIdx.x < kWave) {
+    double ta = 0.0, tb = 0.0;
+    for (int k = threadIdx.x; k < ntile; k += kWave) {
+      ta += pa[k];
+      tb += pb[k];
+    }
+    ta = wsum(ta);
+    tb = wsum(tb);
+    if (threadIdx.x == 0) {
+      slot[0] = ta;
+      slot[1] = tb;
+    }
+  }
+  __syncthreads();
+  a = slot[0];
+  b = slot[1];
+  __syncthreads();
+}
+
 // the same for the one-thread-per-source start kernel
 __device__ __forceinline__ double sum_parts_serial(const double* part, int ntile) {
   double t = 0.0;
@@ -495,7 +531,9 @@ __global__ __launch_bounds__(kMT) void k_cgm_init(const double* __restrict__ kdi
                                                   int ns, int ntile, const double* __restrict__ rhs,
                                                   double* __restrict__ x, CgmState S) {
   __shared__ double red[kMT / kWave];
-  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  int tile, j;
+  if (!xcd_tile(ntile, tile, j)) return;
+  const int i = tile * kMT + threadIdx.x;
   const bool live = i < nc && i != 0;
   const double dg = live ? kdia[13 * size_t(ldk) + i] : 0.0;
   const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
@@ -510,8 +548,8 @@ __global__ __launch_bounds__(kMT) void k_cgm_init(const double* __restrict__ kdi
   const double rz = tile_sum<kMT / kWave>(r * z, red);
   const double rr = tile_sum<kMT / kWave>(r * r, red);
   if (threadIdx.x == 0) {
-    S.part[(size_t(1) * ns + j) * ntile + blockIdx.x] = rz;
-    S.part[(size_t(2) * ns + j) * ntile + blockIdx.x] = rr;
+    S.part[(size_t(1) * ns + j) * ntile + tile] = rz;
+    S.part[(size_t(2) * ns + j) * ntile + tile] = rr;
   }
 }
 
@@ -533,7 +571,7 @@ __global__ void k_cgm_start(int ns, int ntile, int defl, CgmState S) {
 // Two-level correction of the multi-launch solver, z = D^-1 r + Z E^-1 Z^T r:
 // s = Z^T r by one workgroup per (aggregate, source), striding over the
 // aggregate's vertex list in a fixed order; then y = E^-1 s and s.y by one
-// wave per source (r.z = r.D^-1 r + s.y).  Sources already stopped are
+// workgroup per source (r.z = r.D^-1 r + s.y).  Sources already stopped are
 // skipped when live_only is set.
 __global__ __launch_bounds__(kMT) void k_cgm_aggsum(int nc, int ns, int par, int live_only, CoarseDefl d,
                                                     CgmState S) {
@@ -548,23 +586,40 @@ __global__ __launch_bounds__(kMT) void k_cgm_aggsum(int nc, int ns, int par, int
   if (threadIdx.x == 0) S.s[size_t(j) * 64 + a] = t;
 }
 
-__global__ __launch_bounds__(kWave) void k_cgm_ysolve(int ns, int par, int live_only, CoarseDefl d,
-                                                      CgmState S) {
-  const int j = blockIdx.x, t = threadIdx.x;
-  if (live_only && S.flag[3 * j + par]) return;
+// y = E^-1 s and s.y, one workgroup per source: thread (q, t) adds columns
+// [16q, 16q + 16) of row t (E^-1 is symmetric, so column c is read across
+// the lanes: one coalesced load a step, sixteen of them independent), and
+// the four quarters are added in LDS in a fixed order.
+__global__ __launch_bounds__(kMT) void k_cgm_ysolve(int ns, int par, int live_only, CoarseDefl d,
+                                                    CgmState S) {
+  __shared__ double part[kMT / kWave][kWave];
+  const int j = blockIdx.x, t = threadIdx.x & (kWave - 1), q = threadIdx.x / kWave;
+  if (live_only && S.flag[3 * j + par]) return;  // uniform over the workgroup
   const double* sj = S.s + size_t(j) * 64;
   double y = 0.0;
-  if (t < d.na)
-    for (int c = 0; c < d.na; ++c) y += d.einv[t * d.na + c] * sj[c];
-  if (t < d.na) S.y[size_t(j) * 64 + t] = y;
-  const double sy = wsum(t < d.na ? sj[t] * y : 0.0);
-  if (t == 0) S.sy[j] = sy;
+  if (t < d.na) {
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = q * 16 + cc;
+      if (c < d.na) y += d.einv[c * d.na + t] * sj[c];
+    }
+  }
+  part[q][t] = y;
+  __syncthreads();
+  if (q == 0) {
+    y = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    if (t < d.na) S.y[size_t(j) * 64 + t] = y;
+    const double sy = wsum(t < d.na ? sj[t] * y : 0.0);
+    if (t == 0) S.sy[j] = sy;
+  }
 }
 
 // p += Z y after the initial residual (p = D^-1 r from the init kernel)
 __global__ __launch_bounds__(kMT) void k_cgm_pcorr(const double* __restrict__ kdia, int ldk, int ncx, int ncy,
-                                                   int nc, CoarseDefl d, CgmState S) {
-  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+                                                   int nc, int ntile, CoarseDefl d, CgmState S) {
+  int tile, j;
+  if (!xcd_tile(ntile, tile, j)) return;
+  const int i = tile * kMT + threadIdx.x;
   if (i >= nc || i == 0) return;
   if (!(kdia[13 * size_t(ldk) + i] > 0.0)) return;
   const int a = agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy));
@@ -574,10 +629,12 @@ __global__ __launch_bounds__(kMT) void k_cgm_pcorr(const double* __restrict__ kd
 __global__ __launch_bounds__(kMT) void k_cgm_spmv(const double* __restrict__ kdia, int ldk, int ncx,
                                                   int ncy, int ncz, int ns, int ntile, int par,
                                                   CgmState S) {
-  __shared__ double red[kMT / kWave];
+  __shared__ double red[kMT / kWave * kMG];
   const int nc = ncx * ncy * ncz;
-  const int i = blockIdx.x * kMT + threadIdx.x;
-  const int j0 = blockIdx.y * kMG;
+  int tile, grp;
+  if (!xcd_tile(ntile, tile, grp)) return;
+  const int i = tile * kMT + threadIdx.x;
+  const int j0 = grp * kMG;
   const bool live = i < nc && i != 0;
   const int x = i % ncx, y = (i / ncx) % ncy, z = i / (ncx * ncy);
   double k[27];
@@ -588,22 +645,40 @@ __global__ __launch_bounds__(kMT) void k_cgm_spmv(const double* __restrict__ kdi
                     z + dz >= 0 && z + dz < ncz && i + dx + ncx * (dy + ncy * dz) != 0;
     k[o] = in ? kdia[size_t(o) * ldk + i] : 0.0;
   }
+  // The group's sources one after another without a barrier between them
+  // (their loads overlap), then one reduction for all of their p.q.
+  double pq[kMG];
+#pragma unroll
   for (int jj = 0; jj < kMG; ++jj) {
+    pq[jj] = 0.0;
     const int j = j0 + jj;
-    if (j >= ns) break;
-    if (S.flag[3 * j + par]) continue;  // uniform over the workgroup
+    if (j >= ns || S.flag[3 * j + par]) continue;  // uniform over the workgroup
     const double* pj = S.p + size_t(j) * nc;
-    double q = 0.0;
     if (live) {
+      double q = 0.0;
 #pragma unroll
       for (int o = 0; o < 27; ++o) {
         const int off = (o % 3 - 1) + ncx * ((o / 3) % 3 - 1 + ncy * (o / 9 - 1));
         if (k[o] != 0.0) q += k[o] * pj[i + off];
       }
       S.q[size_t(j) * nc + i] = q;
+      pq[jj] = pj[i] * q;
     }
-    const double pq = tile_sum<kMT / kWave>(live ? pj[i] * q : 0.0, red);
-    if (threadIdx.x == 0) S.part[(size_t(0) * ns + j) * ntile + blockIdx.x] = pq;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int jj = 0; jj < kMG; ++jj) {
+    pq[jj] = wsum(pq[jj]);
+    if (lane == 0) red[wid * kMG + jj] = pq[jj];
+  }
+  __syncthreads();
+  if (threadIdx.x < kMG) {
+    const int j = j0 + threadIdx.x;
+    if (j < ns && !S.flag[3 * j + par]) {
+      double t = red[threadIdx.x];
+      for (int w = 1; w < kMT / kWave; ++w) t += red[w * kMG + threadIdx.x];
+      S.part[(size_t(0) * ns + j) * ntile + tile] = t;
+    }
   }
 }
 
@@ -612,7 +687,9 @@ __global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ k
                                                     double* __restrict__ x, CgmState S) {
   __shared__ double red[kMT / kWave];
   __shared__ double slot;
-  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  int tile, j;
+  if (!xcd_tile(ntile, tile, j)) return;
+  const int i = tile * kMT + threadIdx.x;
   if (S.flag[3 * j + par]) return;  // uniform over the workgroup
   const double pq = sum_parts(S.part + (size_t(0) * ns + j) * ntile, ntile, &slot);
   const double alpha = pq != 0.0 ? S.scal[3 * j + par] / pq : 0.0;
@@ -631,8 +708,8 @@ __global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ k
   rz = tile_sum<kMT / kWave>(rz, red);
   rr = tile_sum<kMT / kWave>(rr, red);
   if (threadIdx.x == 0) {
-    S.part[(size_t(1) * ns + j) * ntile + blockIdx.x] = rz;
-    S.part[(size_t(2) * ns + j) * ntile + blockIdx.x] = rr;
+    S.part[(size_t(1) * ns + j) * ntile + tile] = rz;
+    S.part[(size_t(2) * ns + j) * ntile + tile] = rr;
   }
 }
 
@@ -641,22 +718,25 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
                                                      int ncy, int nc, int ns, int ntile, int par, int it,
                                                      double tol2, int maxit, int defl, CoarseDefl d,
                                                      CgmState S, int* status, unsigned long long* work) {
-  __shared__ double slot;
-  const int i = blockIdx.x * kMT + threadIdx.x, j = blockIdx.y;
+  __shared__ double slot[2];
+  int tile, j;
+  if (!xcd_tile(ntile, tile, j)) return;
+  const int i = tile * kMT + threadIdx.x;
   const int nxt = par ^ 1;
   if (S.flag[3 * j + par]) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (tile == 0 && threadIdx.x == 0) {
       S.flag[3 * j + nxt] = 1;
       S.scal[3 * j + nxt] = S.scal[3 * j + par];
     }
     return;
   }
-  const double rz = sum_parts(S.part + (size_t(1) * ns + j) * ntile, ntile, &slot) + (defl ? S.sy[j] : 0.0);
-  const double rr = sum_parts(S.part + (size_t(2) * ns + j) * ntile, ntile, &slot);
+  double rz, rr;
+  sum_parts2(S.part + (size_t(1) * ns + j) * ntile, S.part + (size_t(2) * ns + j) * ntile, ntile, slot, rz, rr);
+  if (defl) rz += S.sy[j];
   const bool conv = rr <= tol2 * S.scal[3 * j + 2];
   const bool bad = rr != rr || (!conv && it >= maxit);
   const bool stop = conv || bad;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (tile == 0 && threadIdx.x == 0) {
     S.flag[3 * j + nxt] = stop ? 1 : 0;
     S.scal[3 * j + nxt] = rz;
     if (stop) {
@@ -736,45 +816,75 @@ hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const d
   S.flag = reinterpret_cast<int*>(S.sy + size_t(ns));
   const bool two = defl && defl->ok && defl->einv && defl->arows && defl->na <= 64;
   const CoarseDefl d = two ? *defl : CoarseDefl();
-  const dim3 gt(ntile, ns), gs(ntile, (ns + kMG - 1) / kMG), ga(two ? d.na : 1, ns);
+  const dim3 gt(xcd_grid(ntile, ns)), gs(xcd_grid(ntile, (ns + kMG - 1) / kMG)), ga(two ? d.na : 1, ns);
   hipLaunchKernelGGL(k_cgm_init, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, rhs, x, S);
   if (two) {
     hipLaunchKernelGGL(k_cgm_aggsum, ga, dim3(kMT), 0, s, nc, ns, 0, 0, d, S);
-    hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kWave), 0, s, ns, 0, 0, d, S);
-    hipLaunchKernelGGL(k_cgm_pcorr, gt, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], nc, d, S);
+    hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kMT), 0, s, ns, 0, 0, d, S);
+    hipLaunchKernelGGL(k_cgm_pcorr, gt, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], nc, ntile, d, S);
   }
   hipLaunchKernelGGL(k_cgm_start, dim3((ns + 255) / 256), dim3(256), 0, s, ns, ntile, two ? 1 : 0, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double tol2 = rtol * rtol;
-  // Phases are issued in chunks; between chunks the host reads the stop
-  // flags (a few bytes) and ends the loop when every source has stopped.
+  // Phases are issued in chunks.  After each chunk the stop flags (a few
+  // bytes) are copied to the host; the host checks them one chunk late, with
+  // the next chunk already queued, so the GPU never waits for the host.  A
+  // chunk queued after every source has stopped only runs early exits.
   constexpr int kChunk = 8;
-  int it = 0, par = 0;
-  while (it < maxit) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (int k = 0; k < 2; ++k) {
+    e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (ev[0]) (void)hipEventDestroy(ev[0]);
+      return e;
+    }
+  }
+  int it = 0, par = 0, pending = -1, pending_par = 0, chunk = 0;
+  auto all_stopped = [&](int buf, int fpar) {
+    const int* f = host_flags + 3 * ns * buf;
+    for (int j = 0; j < ns; ++j)
+      if (f[3 * j + fpar] == 0) return false;
+    return true;
+  };
+  while (e == hipSuccess) {
+    if (it >= maxit) {
+      // the last chunk is queued: wait for it and stop
+      e = hipStreamSynchronize(s);
+      break;
+    }
     for (int c = 0; c < kChunk && it < maxit; ++c, ++it) {
       hipLaunchKernelGGL(k_cgm_spmv, gs, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], ncv[2], ns, ntile,
                          par, S);
       hipLaunchKernelGGL(k_cgm_update, gt, dim3(kMT), 0, s, kdia, ldk, nc, ns, ntile, par, x, S);
       if (two) {
         hipLaunchKernelGGL(k_cgm_aggsum, ga, dim3(kMT), 0, s, nc, ns, par, 1, d, S);
-        hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kWave), 0, s, ns, par, 1, d, S);
+        hipLaunchKernelGGL(k_cgm_ysolve, dim3(ns), dim3(kMT), 0, s, ns, par, 1, d, S);
       }
       hipLaunchKernelGGL(k_cgm_pupdate, gt, dim3(kMT), 0, s, kdia, ldk, ncv[0], ncv[1], nc, ns, ntile, par,
                          it + 1, tol2, maxit, two ? 1 : 0, d, S, status, work);
       par ^= 1;
     }
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(host_flags, S.flag, sizeof(int) * 3 * ns, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    bool all = true;
-    for (int j = 0; j < ns; ++j) all = all && host_flags[3 * j + par] != 0;
-    if (all) break;
+    if (e != hipSuccess) break;
+    const int buf = chunk & 1;
+    e = hipMemcpyAsync(host_flags + 3 * ns * buf, S.flag, sizeof(int) * 3 * ns, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[buf], s);
+    if (e != hipSuccess) break;
+    if (pending >= 0) {
+      e = hipEventSynchronize(ev[pending]);
+      if (e != hipSuccess) break;
+      if (all_stopped(pending, pending_par)) {
+        e = hipStreamSynchronize(s);  // the chunk just queued runs early exits
+        break;
+      }
+    }
+    pending = buf;
+    pending_par = par;
+    ++chunk;
   }
-  return hipSuccess;
+  for (int k = 0; k < 2; ++k) (void)hipEventDestroy(ev[k]);
+  return e;
 }
 
 CoarseDefl coarse_defl_plan_large(const int ncv[3]) {

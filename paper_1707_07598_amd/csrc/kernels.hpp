@@ -111,7 +111,7 @@ hipError_t launch_coarse_defl_setup(const double* kdia, const int ncv[3], const 
 // PCG over all columns, three launches per iteration (five with the
 // two-level correction, when defl is given), and the host polls the stop
 // flags every few iterations (so the call blocks until the solve ends).
-// workspace: coarse_large_workspace bytes of device memory; host_flags: 3*ns
+// workspace: coarse_large_workspace bytes of device memory; host_flags: 6*ns
 // ints of pinned host memory.
 bool coarse_is_large(const int ncv[3]);
 size_t coarse_large_workspace(const int ncv[3], int ns);
