@@ -221,14 +221,18 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_defl_setup(const double* e, Co
 // to ldk = RPT*BLOCK (padding rows have zero diagonals); the search direction
 // p lives in LDS with a zero halo, so the stencil loop has no branches.
 // Row layouts (QM):
-//  * false: thread t owns rows t + q*BLOCK; p in LDS by row;
-//  * true (RPT | Ncx): thread t owns the RPT consecutive rows RPT*t + q, so
+//  * 0: thread t owns rows t + q*BLOCK; p in LDS by row;
+//  * 1 and 2 (RPT = 2, 4, 6): thread t owns the RPT consecutive rows RPT*t + q, so
 //    it loads its coefficients of one offset as RPT contiguous doubles and
-//    shares the x-neighbours of its rows; p in LDS as RPT planes,
-//    row RPT*t + q in plane q, slot t (consecutive lanes, consecutive slots).
+//    shares the x-neighbours of its rows; p in LDS as RPT planes, row j (after
+//    a halo shift) in plane j mod RPT, slot j div RPT (consecutive lanes,
+//    consecutive slots).  The window of a (dy, dz) row shift o starts at
+//    plane o mod RPT, so Ncx need not be a multiple of RPT (layout 2; layout
+//    1 is the same with the plane offsets fixed at compile time, for
+//    RPT | Ncx).
 // With DEFL, the LDS copy of p is reused between the stencil product and the
 // update of p to stage r for the aggregate sums.
-template <int BLOCK, int RPT, bool DEFL, bool QM>
+template <int BLOCK, int RPT, bool DEFL, int QM>
 __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__ kdia, int ldk, int ncx,
                                                       int ncy, int ncz, const double* __restrict__ rhs,
                                                       double* __restrict__ xout, double rtol, int maxit,
@@ -237,18 +241,18 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
   const int nc = ncx * ncy * ncz;
-  const int pad = 1 + ncx + ncx * ncy;
+  const int pad = 1 + ncx + (ncz > 1 ? ncx * ncy : 0);  // a 2-D grid has no z-neighbours
   const int H = pad / RPT + 2;              // QM: halo slots a plane side
   const int plane = BLOCK + 2 * H;          // QM: slots a plane
-  const int pn = QM ? RPT * plane : ldk + 2 * pad;
-  double* p = QM ? lds : lds + pad;
+  const int pn = QM != 0 ? RPT * plane : ldk + 2 * pad;
+  double* p = QM != 0 ? lds : lds + pad;
   // LDS position of row i (any row within the halo)
   auto pos = [=](int i) -> int {
-    if (!QM) return i;
+    if (QM == 0) return i;
     const int jj = i + RPT * H;
     return (jj % RPT) * plane + jj / RPT;
   };
-  auto row = [=](int q) -> int { return QM ? RPT * int(threadIdx.x) + q : int(threadIdx.x) + q * BLOCK; };
+  auto row = [=](int q) -> int { return QM != 0 ? RPT * int(threadIdx.x) + q : int(threadIdx.x) + q * BLOCK; };
   double* redA = lds + pn;
   double* redB = redA + NW * 4;
   double* einv = redB + NW * 4;        // DEFL: na * na
@@ -342,9 +346,10 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
     int lo = threadIdx.x;
     asm volatile("" : "+s"(kb));
     asm volatile("" : "+v"(lo));
-    if (!QM) {
+    if (QM == 0) {
 #pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz) {
+        if (dz != 0 && ncz == 1) continue;  // 2-D: no z-neighbours (and no z-halo)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
@@ -355,18 +360,35 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 #pragma unroll
             for (int q = 0; q < RPT; ++q) ap[q] += kd[q * BLOCK + lo] * p[lo + q * BLOCK + off];
           }
+      }
     } else {
 #pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz) {
+        if (dz != 0 && ncz == 1) continue;  // 2-D: no z-neighbours (and no z-halo)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
-          // window w[s] = p(row RPT*t + off + s), s = -1 .. RPT
-          const int slot = lo + H + (ncx * (dy + ncy * dz)) / RPT;
+          // window w[s] = p(row RPT*t + o + s), s = -1 .. RPT, for the row
+          // shift o = Ncx (dy + Ncy dz) = RPT m + c, 0 <= c < RPT: row
+          // RPT (t + m) + (c + s) sits in plane (c + s) mod RPT, slot
+          // t + m + floor((c + s) / RPT)
           double wv[RPT + 2];
-          wv[0] = p[(RPT - 1) * plane + slot - 1];
+          if (QM == 1) {  // RPT | Ncx: c = 0
+            const int slot = lo + H + (ncx * (dy + ncy * dz)) / RPT;
+            wv[0] = p[(RPT - 1) * plane + slot - 1];
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) wv[q + 1] = p[q * plane + slot];
-          wv[RPT + 1] = p[slot + 1];
+            for (int q = 0; q < RPT; ++q) wv[q + 1] = p[q * plane + slot];
+            wv[RPT + 1] = p[slot + 1];
+          } else {
+            const int oyz = ncx * (dy + ncy * dz);
+            const int m = oyz >= 0 ? oyz / RPT : -((RPT - 1 - oyz) / RPT);
+            const int c = oyz - m * RPT;
+            const int slot = lo + H + m;
+#pragma unroll
+            for (int s = -1; s <= RPT; ++s) {
+              const int e = c + s + RPT;  // in [RPT - 1, 3 RPT)
+              wv[s + 1] = p[(e % RPT) * plane + slot + e / RPT - 1];
+            }
+          }
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
@@ -379,6 +401,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
             }
           }
         }
+      }
     }
     if (owns_pin) ap[0] = 0.0;
     double pq[1] = {0.0};
@@ -758,10 +781,16 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
 
 constexpr int kBlock = 1024;
 
-// RPT consecutive rows a thread (2 or 4, dividing Ncx)
+// LDS halo of the single-workgroup solver: the largest row shift of the
+// stencil (no z-shift on a 2-D grid)
+int coarse_pad(const int ncv[3]) { return 1 + ncv[0] + (ncv[2] > 1 ? ncv[0] * ncv[1] : 0); }
+
+// RPT consecutive rows a thread (2, 4 or 6; at 8 rows a thread the strided
+// layout measured faster: 35 against 39 us an iteration at 19^3 vertices)
 int qm_rows(int ldk, int ncx) {
+  (void)ncx;
   const int rpt = ldk / kBlock;
-  return ((rpt == 2 || rpt == 4) && ncx % rpt == 0) ? rpt : 0;
+  return (rpt == 2 || rpt == 4 || rpt == 6) ? rpt : 0;
 }
 
 size_t pcg_lds_bytes(int ldk, int pad, int na, int qm = 0) {
@@ -776,13 +805,13 @@ size_t setup_lds_bytes(int na) { return 2 * size_t(na) * na * sizeof(double); }
 int coarse_ldk(int nc) {
   const int rpt = (nc + kBlock - 1) / kBlock;
   if (rpt > 16) return rpt * kBlock;  // large systems: no LDS staging, rows just padded
-  const int r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : 16;
+  const int r = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 6 ? 6 : rpt <= 8 ? 8 : 16;
   return r * kBlock;
 }
 
 bool coarse_is_large(const int ncv[3]) {
   const int nc = ncv[0] * ncv[1] * ncv[2];
-  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  const int pad = coarse_pad(ncv);
   const int ldk = coarse_ldk(nc);
   // more than 8 rows a thread spill in the single-workgroup kernel, which
   // then runs slower than the multi-launch solver (measured 2.8x at 21^3)
@@ -907,7 +936,7 @@ CoarseDefl coarse_defl_plan(const int ncv[3]) {
     d.b[kmax] *= 2;
   }
   const int nc = ncv[0] * ncv[1] * ncv[2];
-  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  const int pad = coarse_pad(ncv);
   d.ok = d.na >= 2 && pcg_lds_bytes(coarse_ldk(nc), pad, d.na, qm_rows(coarse_ldk(nc), ncv[0])) <= 160 * 1024 &&
          setup_lds_bytes(d.na) <= 160 * 1024;
   return d;
@@ -952,7 +981,7 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
                              unsigned long long* work, hipStream_t s) {
   if (ncol == 0) return hipSuccess;
   const int nc = ncv[0] * ncv[1] * ncv[2];
-  const int pad = 1 + ncv[0] + ncv[0] * ncv[1];
+  const int pad = coarse_pad(ncv);
   const int ldk = coarse_ldk(nc);
   const bool use = defl && defl->ok && defl->einv && defl->arows;
   const CoarseDefl d = use ? *defl : CoarseDefl();
@@ -970,15 +999,20 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
                        rtol, maxit, d, status, work);
     return hipGetLastError();
   };
-  if (qm == 2) return use ? go(k_coarse_pcg<kBlock, 2, true, true>) : go(k_coarse_pcg<kBlock, 2, false, true>);
-  if (qm == 4) return use ? go(k_coarse_pcg<kBlock, 4, true, true>) : go(k_coarse_pcg<kBlock, 4, false, true>);
+#define MSFV_QM_CASE(R)                                                                                  \
+  if (qm == R) {                                                                                        \
+    if (ncv[0] % R == 0)                                                                                \
+      return use ? go(k_coarse_pcg<kBlock, R, true, 1>) : go(k_coarse_pcg<kBlock, R, false, 1>);        \
+    return use ? go(k_coarse_pcg<kBlock, R, true, 2>) : go(k_coarse_pcg<kBlock, R, false, 2>);          \
+  }
+  MSFV_QM_CASE(2)
+  MSFV_QM_CASE(4)
+  MSFV_QM_CASE(6)
+#undef MSFV_QM_CASE
 #define MSFV_PCG_CASE(R)                                                                          \
-  if (rpt <= R) return use ? go(k_coarse_pcg<kBlock, R, true, false>) : go(k_coarse_pcg<kBlock, R, false, false>);
-  MSFV_PCG_CASE(1)
-  MSFV_PCG_CASE(2)
-  MSFV_PCG_CASE(4)
-  MSFV_PCG_CASE(8)
-  MSFV_PCG_CASE(16)
+  if (rpt <= R) return use ? go(k_coarse_pcg<kBlock, R, true, 0>) : go(k_coarse_pcg<kBlock, R, false, 0>);
+  MSFV_PCG_CASE(1)  // up to 1024 rows
+  MSFV_PCG_CASE(8)  // 6145-8192 rows (2, 4 and 6 rows a thread take the consecutive layouts)
 #undef MSFV_PCG_CASE
   return hipErrorInvalidConfiguration;
 }

@@ -134,7 +134,11 @@ def test_small_2d_workload_parity():
                                     ((64, 64), (3, 4), 4),            # 2-D, 22 x 16
                                     ((128, 64), (4, 4), 3),           # 2-D 32 x 16, odd source count
                                     ((32, 32, 24), (4, 4, 4), 5),     # 8 x 8 x 6
-                                    ((516, 256), (4, 4), 3)])         # 2-D 129 x 64 > 8192: multi-launch
+                                    ((516, 256), (4, 4), 3),          # 2-D 129 x 64 > 8192: multi-launch
+                                    ((52, 52, 52), (4, 4, 4), 3),     # 13^3: 4 rows a thread, 4 does not divide Ncx
+                                    ((68, 68, 68), (4, 4, 4), 2),     # 17^3: 6 rows a thread, 6 does not divide Ncx
+                                    ((384, 184), (4, 4), 2),          # 2-D 96 x 46: 6 rows a thread, 6 | Ncx
+                                    ((340, 340), (4, 4), 2)])         # 2-D 85 x 85: 8 rows a thread, 8 does not divide Ncx
 def test_coarse_preconditioners_parity(n, r, ns):
     """The coarse solvers (two-level aggregate correction, plain Jacobi, and
     the multi-launch Jacobi solver of large grids; above 8192 vertices all
