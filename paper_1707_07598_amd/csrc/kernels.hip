@@ -1184,11 +1184,14 @@ hipError_t launch_local(const LocalParams& p, bool adj, hipStream_t s) {
   const int nu = p.nu_cap;
   if (nu <= 64) return launch_local_t<64, 1, 8>(p, adj, s);
   if (nu <= 128) return launch_local_t<128, 1, 8>(p, adj, s);
-  if (nu <= 256) return launch_local_t<256, 1, 8>(p, adj, s);
+  if (nu <= 256)  // faces (4 corners) solve all their corners in one pass of half the registers
+    return p.nc_cap <= 4 ? launch_local_t<256, 1, 4>(p, adj, s) : launch_local_t<256, 1, 8>(p, adj, s);
   if (nu <= 384) return launch_local_t<384, 1, 8>(p, adj, s);
   if (nu <= 512) return launch_local_t<512, 1, 8>(p, adj, s);
   if (nu <= 1024) return launch_local_t<1024, 1, 4>(p, adj, s);
-  if (nu <= 4096) return launch_local_t<512, 8, 1>(p, adj, s);  // LDS: sigma, one direction, tp
+  // LDS: sigma, one direction, tp (four cells a thread at 1024 threads spilled
+  // more and ran 1.7x slower at r = 16)
+  if (nu <= 4096) return launch_local_t<512, 8, 1>(p, adj, s);
   return hipErrorInvalidConfiguration;
 }
 
