@@ -95,6 +95,43 @@ def test_gradient_parity(n, r, mode):
     prob.close()
 
 
+DEGENERATE = [((4, 4, 4), (4, 4, 4)),  # one coarse vertex, and it is fixed: the solution is zero
+              ((8, 3, 5), (4, 3, 5)),  # two coarse vertices, one free
+              ((5, 5, 5), (4, 4, 4)),  # 2^3 vertices, 1-cell last coarse cells
+              ((9, 7), (4, 3))]        # 2-D, 3 x 3 vertices, no dual blocks of 2 open axes beyond faces
+
+
+@pytest.mark.parametrize("n,r", DEGENERATE)
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_grids_and_sources(n, r, mode):
+    """The smallest grids (down to a single coarse vertex, which is fixed),
+    with a source column that cancels within one cell, a column with a
+    repeated electrode cell and a two-cell receiver: D, t and the gradient
+    match the oracle (zero where the oracle's are zero)."""
+    torch = _torch()
+    import paper_1707_07598_amd as msfv
+    g = Geometry(n, r)
+    N = g.ncell
+    rng = np.random.default_rng(3)
+    m = 0.7 * rng.standard_normal(N)
+    src = W.explicit_columns([[(1, 1.0), (N - 2, -1.0)], [(2, 1.0), (2, -1.0)],
+                              [(0, 0.5), (0, 0.5), (N - 1, -1.0)]])
+    rec = W.explicit_columns([[(0, 1.0)], [(N - 1, 1.0)], [(N // 2, 1.0), (N // 3, -1.0)]])
+    st = R.forward(g, m, src, rec, mode)
+    V = rng.standard_normal(st.D.shape)
+    g_ref = R.jtv(st, V)
+    prob = msfv.Problem(n, r, mode)
+    prob.set_sources(src)
+    prob.set_receivers(rec)
+    D = prob.forward(torch.tensor(m, dtype=torch.float64, device="cuda")).cpu().numpy()
+    _, t = prob.coarse()
+    gg = prob.jtv(torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert _rel(D, st.D.T) < 1e-10
+    assert _rel(t, st.t.T) < 1e-10
+    assert _rel(gg, g_ref) < 1e-8
+    prob.close()
+
+
 def test_misfit_gradient_parity():
     torch = _torch()
     n, r = (16, 12, 10), (4, 3, 5)
