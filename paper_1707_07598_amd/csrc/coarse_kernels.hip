@@ -708,31 +708,48 @@ __global__ __launch_bounds__(kMT) void k_cgm_spmv(const double* __restrict__ kdi
 __global__ __launch_bounds__(kMT) void k_cgm_update(const double* __restrict__ kdia, int ldk, int nc,
                                                     int ns, int ntile, int par,
                                                     double* __restrict__ x, CgmState S) {
-  __shared__ double red[kMT / kWave];
+  __shared__ double red[2 * (kMT / kWave)];
   __shared__ double slot;
   int tile, j;
   if (!xcd_tile(ntile, tile, j)) return;
   const int i = tile * kMT + threadIdx.x;
   if (S.flag[3 * j + par]) return;  // uniform over the workgroup
+  const bool live = i < nc && i != 0;
+  const size_t o = size_t(j) * nc + i;
+  // the row's operands first, so that their loads are in flight while wave 0
+  // sums the partials
+  double pv = 0.0, qv = 0.0, rv = 0.0, xv = 0.0, dinv = 0.0;
+  if (live) {
+    const double dg = kdia[13 * size_t(ldk) + i];
+    dinv = dg > 0.0 ? 1.0 / dg : 0.0;
+    pv = S.p[o];
+    qv = S.q[o];
+    rv = S.r[o];
+    xv = x[o];
+  }
   const double pq = sum_parts(S.part + (size_t(0) * ns + j) * ntile, ntile, &slot);
   const double alpha = pq != 0.0 ? S.scal[3 * j + par] / pq : 0.0;
-  const bool live = i < nc && i != 0;
   double rz = 0.0, rr = 0.0;
   if (live) {
-    const size_t o = size_t(j) * nc + i;
-    const double dg = kdia[13 * size_t(ldk) + i];
-    const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
-    x[o] += alpha * S.p[o];
-    const double r = S.r[o] - alpha * S.q[o];
+    x[o] = xv + alpha * pv;
+    const double r = rv - alpha * qv;
     S.r[o] = r;
     rz = r * r * dinv;
     rr = r * r;
   }
-  rz = tile_sum<kMT / kWave>(rz, red);
-  rr = tile_sum<kMT / kWave>(rr, red);
-  if (threadIdx.x == 0) {
-    S.part[(size_t(1) * ns + j) * ntile + tile] = rz;
-    S.part[(size_t(2) * ns + j) * ntile + tile] = rr;
+  // both tile sums in one pass (waves added in a fixed order)
+  rz = wsum(rz);
+  rr = wsum(rr);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) {
+    red[2 * wid] = rz;
+    red[2 * wid + 1] = rr;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = red[threadIdx.x];
+    for (int w = 1; w < kMT / kWave; ++w) t += red[2 * w + threadIdx.x];
+    S.part[(size_t(1 + threadIdx.x) * ns + j) * ntile + tile] = t;
   }
 }
 
@@ -753,6 +770,17 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
     }
     return;
   }
+  const bool live = i < nc && i != 0;
+  const size_t o = size_t(j) * nc + i;
+  // the row's operands first (in flight while wave 0 sums the partials)
+  double rv = 0.0, pv = 0.0, dinv = 0.0, yv = 0.0;
+  if (live) {
+    const double dg = kdia[13 * size_t(ldk) + i];
+    dinv = dg > 0.0 ? 1.0 / dg : 0.0;
+    rv = S.r[o];
+    pv = S.p[o];
+    if (defl && dinv != 0.0) yv = S.y[size_t(j) * 64 + agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy))];
+  }
   double rz, rr;
   sum_parts2(S.part + (size_t(1) * ns + j) * ntile, S.part + (size_t(2) * ns + j) * ntile, ntile, slot, rz, rr);
   if (defl) rz += S.sy[j];
@@ -768,15 +796,10 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
       if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
     }
   }
-  if (stop || i >= nc || i == 0) return;
+  if (stop || !live) return;
   const double rzo = S.scal[3 * j + par];
   const double beta = rzo != 0.0 ? rz / rzo : 0.0;
-  const size_t o = size_t(j) * nc + i;
-  const double dg = kdia[13 * size_t(ldk) + i];
-  const double dinv = dg > 0.0 ? 1.0 / dg : 0.0;
-  double z = S.r[o] * dinv;
-  if (defl && dinv != 0.0) z += S.y[size_t(j) * 64 + agg_index(d, i % ncx, (i / ncx) % ncy, i / (ncx * ncy))];
-  S.p[o] = z + beta * S.p[o];
+  S.p[o] = (rv * dinv + yv) + beta * pv;
 }
 
 constexpr int kBlock = 1024;
