@@ -458,7 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 // Large coarse systems (more rows than one workgroup can stage in LDS):
 // Jacobi-PCG for all right-hand sides together, one launch per phase:
 //   spmv_dot : q_j = A p_j and per-tile partials of p_j.q_j (the coefficients
-//              of a tile of rows are loaded once for a group of 8 sources);
+//              of a tile of rows are loaded once for a group of kMG sources);
 //   update   : alpha_j from the partials, x_j += alpha p_j, r_j -= alpha q_j,
 //              partials of r_j.z_j and r_j.r_j (z = D^-1 r);
 //   pupdate  : beta_j and the stop test from the partials, p_j = z_j + beta p_j.
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 // agree bit for bit without a separate scalar launch.  Per-source scalars
 // that a phase both reads and writes are double-buffered by iteration parity.
 constexpr int kMT = 256;  // rows per tile (one per thread)
-constexpr int kMG = 8;    // sources per spmv workgroup
+constexpr int kMG = 4;    // sources per stencil workgroup (8: 39 us, 4: 28 us, 2: 33 us, 1: 37 us at 36^3, 27 sources)
 
 // The per-row kernels run on a 1-D grid whose workgroups go round-robin over
 // the eight XCDs (linear id mod 8).  Linear id L maps to (tile, column) so
