@@ -364,9 +364,13 @@ __device__ __forceinline__ void load_column(const EntDesc& E, const WGeo& w, boo
 // Conjugate gradients on the scaled operator for one corner, run by one
 // wavefront.  y holds the scaled right-hand side on entry and the scaled
 // solution on exit.  pbuf: this wave's padded plane buffer.
+// With a start vector (x0 != nullptr, the scaled initial guess), the
+// iteration starts from r = y - A x0 and the stop test stays relative to the
+// right-hand side y, as without one.
 template <int LMAX>
 __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
-                       double (&y)[LMAX], double* pbuf, double tol2, int maxit, bool* ok) {
+                       double (&y)[LMAX], double* pbuf, double tol2, int maxit, bool* ok,
+                       const double (*x0)[LMAX] = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < w.plane * w.L; i += kWave) pbuf[i] = 0.0;
   wave_sync_lds();
@@ -386,6 +390,31 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
   int it = 0;
   *ok = true;
   if (!(bb > 0.0)) return 0;
+  if (x0) {
+    // r = y - A x0 (the in-plane neighbours of x0 through the plane buffer)
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k)
+        if (k < w.L) pbuf[k * w.plane + pidx] = (*x0)[k];
+    }
+    wave_sync_lds();
+    rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      double s = (*x0)[k];
+      if (k > 0) s -= C.tz[k - 1] * (*x0)[k - 1];
+      if (k + 1 < LMAX) s -= C.tz[k] * (*x0)[k + 1];
+      const double* pl = pbuf + min(k, w.L - 1) * w.plane + pidx_safe;
+      s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
+      r[k] -= s;
+      p[k] = r[k];
+      y[k] = (*x0)[k];
+      rr += r[k] * r[k];
+    }
+    rr = wsum(rr);
+    wave_sync_lds();  // all lanes finished reading x0 before the loop writes p
+    if (rr <= tol2 * bb) return 0;
+  }
   while (true) {
     if (it >= maxit) {
       *ok = false;
@@ -718,6 +747,56 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
       y[k] = b / S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
     }
   };
+  // Start vector of a dual block bounded by vertex planes on all three axes:
+  // the transfinite (Gordon-Hall) interpolation of corner c's values on the
+  // closure boundary, i.e. the sum of the three one-axis linear blends between
+  // opposite faces, minus the three two-axis blends between edges, plus the
+  // trilinear blend of the eight vertex cells (index coordinates, planes at 0
+  // and U+1 on each axis); scaled like the unknowns.  On the 128^3 field it
+  // leaves about 4e-4 of the right-hand side as initial residual, against
+  // 0.12 for the trilinear Lagrange values.
+  const bool guess = E.bounded_mask == 7 && w.L <= LMAX;
+  auto coons = [&](int c, int ia, int ib, double (&x0)[LMAX]) {
+    const int A = w.Ua + 1, B = w.Ub + 1, Cc = w.L + 1;
+    const double* f = S.phi + c * ncl;
+    // closure index of closure coordinates (pa, pb, pc); own cell (0,0,0) is (1,1,1)
+    auto at = [&](int pa, int pb, int pc) {
+      return f[w.s0 + (pa - 1) * w.sa + (pb - 1) * w.sb + (pc - 1) * w.sc];
+    };
+    const int ja = ia + 1, jb = ib + 1;
+    const double xa = double(ja) / A, xb = double(jb) / B;
+    // the parts that do not depend on the column position
+    const double fc0 = at(ja, jb, 0), fc1 = at(ja, jb, Cc);
+    const double e00 = at(ja, 0, 0), e10 = at(ja, B, 0), e01 = at(ja, 0, Cc), e11 = at(ja, B, Cc);
+    const double g00 = at(0, jb, 0), g10 = at(A, jb, 0), g01 = at(0, jb, Cc), g11 = at(A, jb, Cc);
+    double v[2][2][2];
+#pragma unroll
+    for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+      for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int sc = 0; sc < 2; ++sc) v[sa][sb][sc] = at(sa * A, sb * B, sc * Cc);
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+      x0[k] = 0.0;
+      if (!valid || k >= w.L) continue;
+      const int jc = k + 1;
+      const double xc = double(jc) / Cc;
+      const double pa = (1 - xa) * at(0, jb, jc) + xa * at(A, jb, jc);
+      const double pb = (1 - xb) * at(ja, 0, jc) + xb * at(ja, B, jc);
+      const double pc = (1 - xc) * fc0 + xc * fc1;
+      const double pab = (1 - xa) * ((1 - xb) * at(0, 0, jc) + xb * at(0, B, jc)) +
+                         xa * ((1 - xb) * at(A, 0, jc) + xb * at(A, B, jc));
+      const double pbc = (1 - xb) * ((1 - xc) * e00 + xc * e01) + xb * ((1 - xc) * e10 + xc * e11);
+      const double pac = (1 - xa) * ((1 - xc) * g00 + xc * g01) + xa * ((1 - xc) * g10 + xc * g11);
+      const double pabc =
+          (1 - xa) * ((1 - xb) * ((1 - xc) * v[0][0][0] + xc * v[0][0][1]) +
+                      xb * ((1 - xc) * v[0][1][0] + xc * v[0][1][1])) +
+          xa * ((1 - xb) * ((1 - xc) * v[1][0][0] + xc * v[1][0][1]) + xb * ((1 - xc) * v[1][1][0] + xc * v[1][1][1]));
+      const double xv = pa + pb + pc - pab - pbc - pac + pabc;
+      x0[k] = xv * S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
+    }
+  };
   // corner c's values on the own cells (unscaled solution, or the Lagrange
   // values of a prescribed entity) to S_k and to the LDS basis table
   auto store = [&](int c, int ia, int ib, const double (&y)[LMAX]) {
@@ -782,7 +861,14 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
       if (!a.prescribe) {
         rhs(c, ia, ib, y);
         bool ok = true;
-        const int it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+        int it;
+        if (guess) {
+          double x0[LMAX];
+          coons(c, ia, ib, x0);
+          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok, &x0);
+        } else {
+          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+        }
         if (lane == 0) {
           S.wit[c] = it;
           if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
