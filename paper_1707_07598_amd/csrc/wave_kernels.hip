@@ -510,7 +510,7 @@ __device__ __forceinline__ void reduce4(double (&v)[4]) {
 template <int LMAX>
 __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
                          double (&y)[4][LMAX], double* buf, int plane_cap, double tol2, int maxit,
-                         int (&its)[4], bool (&ok)[4]) {
+                         int (&its)[4], bool (&ok)[4], const double (*x0)[4][LMAX] = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < 4 * plane_cap; i += kWave) buf[i] = 0.0;
   wave_sync_lds();
@@ -535,6 +535,45 @@ __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column
     done[c] = !(bb[c] > 0.0);
     its[c] = 0;
     ok[c] = true;
+  }
+  if (x0) {
+    // start vectors (a corner with a zero right-hand side keeps a zero
+    // start): r = y - A x0, the stop test still relative to y
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k)
+          if (k < w.L) buf[c * plane_cap + k * w.plane + pidx] = done[c] ? 0.0 : (*x0)[c][k];
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      rr[c] = 0.0;
+      if (done[c]) continue;
+#pragma unroll
+      for (int k = 0; k < LMAX; ++k) {
+        double s = (*x0)[c][k];
+        if (k > 0) s -= C.tz[k - 1] * (*x0)[c][k - 1];
+        if (k + 1 < LMAX) s -= C.tz[k] * (*x0)[c][k + 1];
+        const double* pl = buf + c * plane_cap + min(k, w.L - 1) * w.plane + pidx_safe;
+        s -= C.tam[k] * pl[-1] + C.tap[k] * pl[1] + C.tbm[k] * pl[-w.pa] + C.tbp[k] * pl[w.pa];
+        r[c][k] -= s;
+        p[c][k] = r[c][k];
+        y[c][k] = (*x0)[c][k];
+        rr[c] += r[c][k] * r[c][k];
+      }
+    }
+    reduce4(rr);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (!done[c] && rr[c] <= tol2 * bb[c]) {
+        done[c] = true;
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) p[c][k] = 0.0;
+      }
+    }
+    wave_sync_lds();  // all lanes finished reading the start vectors
   }
   int it = 0;
   while (!(done[0] && done[1] && done[2] && done[3])) {
@@ -797,6 +836,24 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
       x0[k] = xv * S.dsq[ia * w.ua + ib * w.ub + k * w.uc];
     }
   };
+  // The same for an entity of one cell a lane (faces, and dual blocks of a
+  // 2-D grid) bounded on both of its open axes: the bilinear (Coons) blend
+  // of the corner's values on the four sides of the closure.
+  const bool guess2 = LMAX == 1 && w.L == 1 && E.bounded_mask == E.open_mask && __popc(E.open_mask) == 2;
+  auto coons2 = [&](int c, int ia, int ib, double (&x0)[LMAX]) {
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) x0[k] = 0.0;
+    if (c >= nc || !valid) return;
+    const int A = w.Ua + 1, B = w.Ub + 1;
+    const double* f = S.phi + c * ncl;
+    auto at = [&](int pa, int pb) { return f[w.s0 + (pa - 1) * w.sa + (pb - 1) * w.sb]; };
+    const int ja = ia + 1, jb = ib + 1;
+    const double xa = double(ja) / A, xb = double(jb) / B;
+    const double pa = (1 - xa) * at(0, jb) + xa * at(A, jb);
+    const double pb = (1 - xb) * at(ja, 0) + xb * at(ja, B);
+    const double pab = (1 - xa) * ((1 - xb) * at(0, 0) + xb * at(0, B)) + xa * ((1 - xb) * at(A, 0) + xb * at(A, B));
+    x0[0] = (pa + pb - pab) * S.dsq[ia * w.ua + ib * w.ub];
+  };
   // corner c's values on the own cells (unscaled solution, or the Lagrange
   // values of a prescribed entity) to S_k and to the LDS basis table
   auto store = [&](int c, int ia, int ib, const double (&y)[LMAX]) {
@@ -836,7 +893,14 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
       }
       int its[4];
       bool ok[4];
-      wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+      if (guess2) {
+        double x0[4][LMAX];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) coons2(c, ia0, ib0, x0[c]);
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok, &x0);
+      } else {
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+      }
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
