@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances: S_k, A_k, t, D and u within 1e-10 relative (Frobenius), the
-gradient within 1e-8 relative, as stated for this path; both sides compute
-in FP64.  Grids span several dual blocks, truncated last coarse cells
+Tolerances: S_k, A_k, t, D and u within 1e-10 relative, the gradient within
+1e-8 relative, as stated for this path; both sides compute in FP64.  t, D
+and u are compared source by source and element-wise (``_parity.rows``), the
+gradient as a whole and split by source (J^T applied to one source's
+residual column at a time), S_k and A_k entry by entry.  Grids span several dual blocks, truncated last coarse cells
 (n mod r != 0), empty upper strips (last coarse cell of 1 or 2 cells), both
 boundary modes, 2-D and 3-D.
 """
@@ -10,6 +12,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import _parity as PT
 import workloads as W
 from oracle import Geometry
 from oracle import reduced as R
@@ -42,11 +45,6 @@ def _problem(n, r, mode, inst, **kw):
     return prob
 
 
-def _rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
 def _csr(rp, col, val, shape):
     return sp.csr_matrix((val, col, rp), shape=shape)
 
@@ -65,15 +63,15 @@ def test_forward_parity(n, r, mode):
     rp, col, val = prob.prolongation()
     P = _csr(rp, col, val, (g.ncell, g.ncoarse)).toarray()
     Pref = st.P.toarray()
-    assert _rel(P, Pref) < 1e-10
     assert np.abs(P - Pref).max() < 1e-10
-    # A_k before the pin
+    PT.rows(P.T, Pref.T, 1e-10, "S_k columns")
+    # A_k before the pin, row by row
     (krp, kcol, kval), t = prob.coarse()
     K = _csr(krp, kcol, kval, (g.ncoarse, g.ncoarse)).toarray()
-    assert _rel(K, st.K) < 1e-10
-    assert _rel(t, st.t.T) < 1e-10
-    assert _rel(D.cpu().numpy(), st.D.T) < 1e-10
-    assert _rel(u.cpu().numpy(), st.u.T) < 1e-10
+    PT.rows(K, st.K, 1e-10, "A_k rows")
+    PT.rows(t, st.t.T, 1e-10, "t")
+    PT.rows(D.cpu().numpy(), st.D.T, 1e-10, "D")
+    PT.rows(u.cpu().numpy(), st.u.T, 1e-10, "u")
     prob.close()
 
 
@@ -91,7 +89,8 @@ def test_gradient_parity(n, r, mode):
     m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
     prob.forward(m)
     gg = prob.jtv(torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")).cpu().numpy()
-    assert _rel(gg, g_ref) < 1e-8
+    PT.vector(gg, g_ref, 1e-8, "g")
+    PT.gradient_per_source(prob, st, V, 1e-8)
     prob.close()
 
 
@@ -126,9 +125,10 @@ def test_degenerate_grids_and_sources(n, r, mode):
     D = prob.forward(torch.tensor(m, dtype=torch.float64, device="cuda")).cpu().numpy()
     _, t = prob.coarse()
     gg = prob.jtv(torch.tensor(V.T.copy(), dtype=torch.float64, device="cuda")).cpu().numpy()
-    assert _rel(D, st.D.T) < 1e-10
-    assert _rel(t, st.t.T) < 1e-10
-    assert _rel(gg, g_ref) < 1e-8
+    PT.rows(D, st.D.T, 1e-10, "D")
+    PT.rows(t, st.t.T, 1e-10, "t")
+    PT.vector(gg, g_ref, 1e-8, "g")
+    PT.gradient_per_source(prob, st, V, 1e-8)
     prob.close()
 
 
@@ -143,7 +143,7 @@ def test_misfit_gradient_parity():
     m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
     phi, gg = prob.misfit_grad(m, torch.tensor(Dobs.T.copy(), dtype=torch.float64, device="cuda"))
     assert abs(phi.item() - phi_ref) <= 1e-10 * abs(phi_ref)
-    assert _rel(gg.cpu().numpy(), g_ref) < 1e-8
+    PT.vector(gg.cpu().numpy(), g_ref, 1e-8, "g")
     prob.close()
 
 
@@ -158,9 +158,9 @@ def test_small_2d_workload_parity():
     prob = _problem(inst.n, inst.r, "reduced", inst)
     m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
     D = prob.forward(m)
-    assert _rel(D.cpu().numpy(), st.D.T) < 1e-10
+    PT.rows(D.cpu().numpy(), st.D.T, 1e-10, "D")
     gg = prob.jtv(torch.tensor((st.D - Dobs).T.copy(), dtype=torch.float64, device="cuda"))
-    assert _rel(gg.cpu().numpy(), g_ref) < 1e-8
+    PT.vector(gg.cpu().numpy(), g_ref, 1e-8, "g")
     prob.close()
 
 
@@ -197,13 +197,13 @@ def test_coarse_preconditioners_parity(n, r, ns):
         _, t = prob.coarse()
         gg = prob.jtv(Vd).cpu().numpy()
         out[pc] = (D, t, gg, prob.stats().coarse_max_it)
-        assert _rel(D, st.D.T) < 1e-10
-        assert _rel(t, st.t.T) < 1e-10
-        assert _rel(gg, g_ref) < 1e-8
+        PT.rows(D, st.D.T, 1e-10, f"D ({pc})")
+        PT.rows(t, st.t.T, 1e-10, f"t ({pc})")
+        PT.vector(gg, g_ref, 1e-8, f"g ({pc})")
         prob.close()
     for pc in ("jacobi", "multi"):
-        assert _rel(out["twolevel"][0], out[pc][0]) < 1e-11
-        assert _rel(out["twolevel"][2], out[pc][2]) < 1e-9
+        PT.rows(out[pc][0], out["twolevel"][0], 1e-11, f"D twolevel vs {pc}")
+        PT.vector(out[pc][2], out["twolevel"][2], 1e-9, f"g twolevel vs {pc}")
     assert out["twolevel"][3] < out["jacobi"][3]
 
 
@@ -267,7 +267,7 @@ def test_autograd_function():
     phi = msfv.msfv_misfit(m, prob, dobs)
     phi.backward()
     _, g_ref, _ = R.misfit_grad(g, inst.m, inst.sources, inst.receivers, Dobs)
-    assert _rel(m.grad.cpu().numpy(), g_ref) < 1e-8
+    PT.vector(m.grad.cpu().numpy(), g_ref, 1e-8, "g")
     # directional finite difference through the Function
     e = torch.tensor(np.random.default_rng(5).standard_normal(g.ncell), device="cuda")
     h = 1e-5

@@ -6,6 +6,7 @@ difference of D at the 128^3 benchmark size, and the error paths."""
 import numpy as np
 import pytest
 
+import _parity as PT
 import workloads as W
 from oracle import Geometry
 from oracle import reduced as R
@@ -51,11 +52,12 @@ def test_sensitivities_match_oracle(n, r, mode):
     dmt = torch.tensor(dm, device="cuda")
     Vt = torch.tensor(V.T.copy(), device="cuda")
     jv = prob.jvp(dmt).cpu().numpy()
-    assert _rel(jv, R.jvp(st, dm).T) < 1e-8
+    PT.rows(jv, R.jvp(st, dm).T, 1e-8, "J dm")
     jvf = prob.jvp(dmt, fixed=True).cpu().numpy()
-    assert _rel(jvf, R.jvp_fixed(st, dm).T) < 1e-8
+    PT.rows(jvf, R.jvp_fixed(st, dm).T, 1e-8, "J dm (fixed)")
     gf = prob.jtv_fixed(Vt).cpu().numpy()
-    assert _rel(gf, R.jtv_fixed(st, V)) < 1e-8
+    PT.vector(gf, R.jtv_fixed(st, V), 1e-8, "J^T v (fixed)")
+    PT.gradient_per_source(prob, st, V, 1e-8, fixed=True)
     # dot identities on the device
     gt = prob.jtv(Vt).cpu().numpy()
     lhs, rhs = float(np.sum(jv * V.T)), float(dm @ gt)
@@ -143,7 +145,8 @@ def test_fixed_versus_adaptive_two_block_model():
         dmt = torch.tensor(dm, device="cuda")
         ja = prob.jvp(dmt).cpu().numpy().T
         jx = prob.jvp(dmt, fixed=True).cpu().numpy().T
-        assert _rel(ja, R.jvp(st, dm)) < 1e-8 and _rel(jx, R.jvp_fixed(st, dm)) < 1e-8
+        PT.rows(ja.T, R.jvp(st, dm).T, 1e-8, f"J dm ({name})")
+        PT.rows(jx.T, R.jvp_fixed(st, dm).T, 1e-8, f"J dm fixed ({name})")
         jf = R.fine_jvp(fs, dm)
         errs[name] = (_rel(ja, jf), _rel(jx, jf), _rel(ja, jx))
     assert errs["uniform"][2] < 1e-9
