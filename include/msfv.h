@@ -254,28 +254,60 @@ msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const dou
 /* ---- Serving ----------------------------------------------------------------
  * A server runs forward (eq. fwdProbRed) + J_k^T v (Sec. 4.3) requests for
  * registered jobs -- the per-iteration evaluations of many concurrent
- * inversions (Sec. 2.2) -- as they arrive.  A dispatcher thread owned by the
- * server takes queued requests first come first served, skipping those
- * whose job is still busy (a job's requests share its problem state and run
- * one at a time, in order); up to max_inflight requests of different jobs
- * run concurrently, each on its job's stream.  Completion is detected with
- * HIP events; latency = completion - submission (steady clock).
+ * inversions (Sec. 2.2) -- as they arrive (continuous batching).  Each job
+ * keeps its problem state (S_k, A_k, plan, workspace) resident on the device
+ * and has a host worker thread of its own that prepares and issues its
+ * requests on the job's stream, so one job's host work (a new source set's
+ * electrode tables, the host-polled coarse solver of large grids) never
+ * holds up another's.  Requests are admitted first come first served when
+ *   - their job is idle (a job's requests share its problem state and run
+ *     one at a time, in order),
+ *   - fewer than max_inflight requests are running, and
+ *   - the resident bytes of all jobs plus the admission bytes of the running
+ *     requests and of this one stay within the memory budget;
+ * no request is admitted past one that waits for memory.  Latency =
+ * completion - submission (steady clock); each request also records device
+ * times of its first and last kernel.
  *
- * msfv_server_create : max_inflight in [1, 64].
- * msfv_server_add_job : registers a caller-owned problem (receivers set;
- *                     give every job its own stream for concurrency).  The
- *                     server uses it exclusively until destroyed.
+ * Admission bytes.  A job's resident bytes are the device bytes its problem
+ * holds once its source-count-dependent buffers are reserved for
+ * max_sources sources (coarse vectors 3 Nc Ns, data buffers 2 Nr Ns, the
+ * multi-launch coarse workspace).  A request's bytes are its device buffers:
+ * m and g (N values each), v and d_out (Nr Ns values each), 16 (N + Nr Ns).
+ *
+ * msfv_server_create : max_inflight in [1, 64]; budget_bytes > 0 is the
+ *                     memory budget, <= 0 the device's total memory.
+ * msfv_server_add_job : registers a caller-owned problem (receivers set; give
+ *                     every job its own stream for concurrency) for requests
+ *                     of up to max_sources sources, reserving its buffers for
+ *                     them.  ENOMEM if the resident bytes of the jobs would
+ *                     exceed the budget (the job is not added).  The server
+ *                     uses the problem exclusively until destroyed.
+ * msfv_server_request_bytes : a job's resident bytes and the admission bytes
+ *                     of a request of ns sources.
  * msfv_server_submit : copies the request's sources (host CSR columns, as
  *                     msfv_set_sources) and queues it; m (N), v (Nr*ns) are
  *                     device inputs and d_out (Nr*ns), g_out (N) device
  *                     outputs that must stay valid until the request is done.
- *                     Returns its id in *req.  EINVAL on bad arguments.
+ *                     The request is ordered after the work queued so far on
+ *                     caller_stream (a hipStream_t; NULL = the null stream),
+ *                     which may be producing m and v.  Returns its id in
+ *                     *req.  EINVAL on bad arguments or ns outside
+ *                     [1, max_sources]; ENOMEM if the request alone (with the
+ *                     jobs' resident bytes) exceeds the budget: it could
+ *                     never be admitted and is rejected.
  * msfv_server_wait   : blocks until request req is done; returns its status
- *                     and, if latency_ms is not NULL, its latency.
- * msfv_server_drain  : blocks until every submitted request is done.
+ *                     and, for non-NULL pointers, its latency and the device
+ *                     times (ms since the server's creation) at which its
+ *                     job's stream reached its first kernel and finished its
+ *                     last.  Several threads may wait for one request.
+ * msfv_server_drain  : blocks until every submitted request is done, then
+ *                     forgets completed requests that nobody waits for.
  * msfv_server_stats  : latency percentiles and throughput of the requests
- *                     completed since the last reset (reset clears them).
- * msfv_server_destroy: drains, stops the dispatcher, releases the server. */
+ *                     completed since the last reset, rejections, the budget,
+ *                     the jobs' resident bytes and the peak of resident plus
+ *                     running-request bytes (reset clears them).
+ * msfv_server_destroy: drains, stops the job workers, releases the server. */
 typedef struct msfv_server msfv_server;
 typedef struct {
   long long completed;   /* requests completed since the last reset        */
@@ -283,14 +315,21 @@ typedef struct {
   double p50_ms, p90_ms, p99_ms, mean_ms, max_ms;  /* latency              */
   double span_s;         /* first submission to last completion            */
   double throughput;     /* completed / span_s (requests per second)       */
+  long long rejected;    /* submissions refused for the memory budget      */
+  double budget_bytes;   /* the memory budget                              */
+  double resident_bytes; /* resident bytes of the registered jobs          */
+  double peak_committed_bytes; /* peak of resident + running-request bytes */
 } msfv_serve_stats;
-msfv_status msfv_server_create(int max_inflight, msfv_server** out);
+msfv_status msfv_server_create(int max_inflight, double budget_bytes, msfv_server** out);
 void msfv_server_destroy(msfv_server* s);
-msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int* job);
+msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int max_sources, int* job);
+msfv_status msfv_server_request_bytes(msfv_server* s, int job, int ns, long long* resident,
+                                      long long* request);
 msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, const int* cell,
                                const double* val, const double* m, const double* v, double* d_out,
-                               double* g_out, long long* req);
-msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms);
+                               double* g_out, void* caller_stream, long long* req);
+msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms, double* dev_start_ms,
+                             double* dev_end_ms);
 msfv_status msfv_server_drain(msfv_server* s);
 msfv_status msfv_server_stats(msfv_server* s, msfv_serve_stats* out, int reset);
 

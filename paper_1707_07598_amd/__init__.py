@@ -355,11 +355,21 @@ class Batch:
         self._gp = _ptr_array(self.g)
 
     def _check_inputs(self, ms, vs):
+        torch = _torch()
         if len(ms) != len(self.problems) or len(vs) != len(self.problems):
             raise ValueError("one m and one v per problem")
         for p, m, v in zip(self.problems, ms, vs):
             p._check_tensor(m, int(np.prod(p.n)), "m")
             p._check_tensor(v, p._ns * p._nr, "v")
+        # a problem's sources or receivers may have changed since the last
+        # call: the library writes Nr * Ns values into D[i]
+        stale = False
+        for i, p in enumerate(self.problems):
+            if tuple(self.D[i].shape) != (p._ns, p._nr):
+                self.D[i] = torch.empty((p._ns, p._nr), dtype=torch.float64, device=self.D[i].device)
+                stale = True
+        if stale:
+            self._dp = _ptr_array(self.D)
 
     def forward_jtv(self, ms, vs, sync: bool = True):
         """D_i = F(m_i) and g_i = J(m_i)^T v_i for every problem i."""
@@ -407,27 +417,45 @@ class Batch:
 
 class Server:
     """Serving runtime (``msfv_server_*``): forward + J^T v requests of
-    registered jobs, dispatched by a native thread as they arrive, up to
-    ``max_inflight`` jobs at once, each on its job's stream."""
+    registered jobs, admitted first come first served as jobs, in-flight
+    slots (``max_inflight``) and the device-memory budget (``hbm_budget``
+    bytes; None = the device's memory) allow; each job's requests are
+    prepared and issued by a native worker thread of its own on the job's
+    stream."""
 
-    def __init__(self, max_inflight: int = 8):
+    def __init__(self, max_inflight: int = 8, hbm_budget: Optional[float] = None):
         self.lib = _lib.load()
         h = ctypes.c_void_p()
-        _lib.check(self.lib.msfv_server_create(int(max_inflight), ctypes.byref(h)), "msfv_server_create")
+        _lib.check(self.lib.msfv_server_create(int(max_inflight), float(hbm_budget or 0.0), ctypes.byref(h)),
+                   "msfv_server_create")
         self._h = h
         self._jobs = []
         self._live = {}
+        self.device_times = {}
 
-    def add_job(self, problem: "Problem") -> int:
+    def add_job(self, problem: "Problem", max_sources: int = 64) -> int:
+        """Register ``problem`` for requests of up to ``max_sources`` sources."""
         j = ctypes.c_int()
-        _lib.check(self.lib.msfv_server_add_job(self._h, problem._h, ctypes.byref(j)),
+        _lib.check(self.lib.msfv_server_add_job(self._h, problem._h, int(max_sources), ctypes.byref(j)),
                    "msfv_server_add_job")
         self._jobs.append(problem)
         return j.value
 
-    def submit(self, job: int, sources, m, v, d_out, g_out) -> int:
+    def request_bytes(self, job: int, ns: int) -> Tuple[int, int]:
+        """(resident bytes of the job, admission bytes of a request of ns sources)."""
+        res, req = ctypes.c_longlong(), ctypes.c_longlong()
+        _lib.check(self.lib.msfv_server_request_bytes(self._h, int(job), int(ns), ctypes.byref(res),
+                                                      ctypes.byref(req)), "msfv_server_request_bytes")
+        return res.value, req.value
+
+    def submit(self, job: int, sources, m, v, d_out, g_out, stream=None) -> int:
         """Queue forward + J^T v of job ``job`` with these sources (host
-        CSR-over-columns ptr/cell/val); tensors stay referenced until done."""
+        CSR-over-columns ptr/cell/val), ordered after the work queued so far
+        on ``stream`` (default: the current stream); tensors stay referenced
+        until the request is done."""
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(m.device)
         ptr = np.ascontiguousarray(sources.ptr, dtype=np.int32)
         cell = np.ascontiguousarray(sources.cell, dtype=np.int32)
         val = np.ascontiguousarray(sources.val, dtype=np.float64)
@@ -437,16 +465,20 @@ class Server:
             ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
             cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
             val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-            _dptr(m), _dptr(v), _dptr(d_out), _dptr(g_out), ctypes.byref(rid)), "msfv_server_submit")
+            _dptr(m), _dptr(v), _dptr(d_out), _dptr(g_out), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.byref(rid)), "msfv_server_submit")
         self._live[rid.value] = (m, v, d_out, g_out)
         return rid.value
 
     def wait(self, req: int) -> float:
-        """Block until request ``req`` is done; its latency in ms."""
-        lat = ctypes.c_double()
+        """Block until request ``req`` is done; its latency in ms.  The device
+        times (ms since the server's creation) of its first and last kernel
+        are kept in ``device_times[req]``."""
+        lat, t0, t1 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         try:
-            _lib.check(self.lib.msfv_server_wait(self._h, ctypes.c_longlong(req), ctypes.byref(lat)),
-                       "msfv_server_wait")
+            _lib.check(self.lib.msfv_server_wait(self._h, ctypes.c_longlong(req), ctypes.byref(lat),
+                                                 ctypes.byref(t0), ctypes.byref(t1)), "msfv_server_wait")
+            self.device_times[req] = (t0.value, t1.value)
         finally:
             self._live.pop(req, None)
         return lat.value

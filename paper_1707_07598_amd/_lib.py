@@ -51,7 +51,9 @@ class MsfvServeStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
                 ("p50_ms", ctypes.c_double), ("p90_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("span_s", ctypes.c_double),
-                ("throughput", ctypes.c_double)]
+                ("throughput", ctypes.c_double), ("rejected", ctypes.c_longlong),
+                ("budget_bytes", ctypes.c_double), ("resident_bytes", ctypes.c_double),
+                ("peak_committed_bytes", ctypes.c_double)]
 
 
 class MsfvStats(ctypes.Structure):
@@ -102,12 +104,14 @@ SIGNATURES = {
     "msfv_batch_get_options": (_I, [_P, _IP, _IP]),
     "msfv_batch_autotune": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                  ctypes.POINTER(_P), _IP, _IP]),
-    "msfv_server_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "msfv_server_create": (_I, [_I, ctypes.c_double, ctypes.POINTER(_P)]),
     "msfv_server_destroy": (None, [_P]),
-    "msfv_server_add_job": (_I, [_P, _P, _IP]),
-    "msfv_server_submit": (_I, [_P, _I, _I, _IP, _IP, _DP, _P, _P, _P, _P,
+    "msfv_server_add_job": (_I, [_P, _P, _I, _IP]),
+    "msfv_server_request_bytes": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_longlong)]),
+    "msfv_server_submit": (_I, [_P, _I, _I, _IP, _IP, _DP, _P, _P, _P, _P, _P,
                                 ctypes.POINTER(ctypes.c_longlong)]),
-    "msfv_server_wait": (_I, [_P, ctypes.c_longlong, _DP]),
+    "msfv_server_wait": (_I, [_P, ctypes.c_longlong, _DP, _DP, _DP]),
     "msfv_server_drain": (_I, [_P]),
     "msfv_server_stats": (_I, [_P, ctypes.POINTER(MsfvServeStats), _I]),
     "msfv_status_string": (ctypes.c_char_p, [_I]),

@@ -149,6 +149,7 @@ struct msfv_problem {
   // large coarse systems: solver workspace and pinned stop flags
   DevBuf<double> d_cg_ws;
   int* h_flags = nullptr;
+  int flags_cap = 0;  // sources h_flags has room for
   ~msfv_problem() {
     if (h_flags) (void)hipHostFree(h_flags);
   }
@@ -347,9 +348,13 @@ msfv_status build_electrodes(msfv_problem* p) {
   HIP_OK(p->d_v.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
   if (coarse_multi(p)) {
     HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, std::max(1, ns)) / sizeof(double) + 1));
-    if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
-    p->h_flags = nullptr;
-    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * std::max(1, ns)));
+    if (p->flags_cap < ns) {  // grow only: freeing pinned memory synchronises the device
+      if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
+      p->h_flags = nullptr;
+      p->flags_cap = 0;
+      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * std::max(1, ns)));
+      p->flags_cap = std::max(1, ns);
+    }
   }
   HIP_OK(hipStreamSynchronize(s));  // host vectors above are temporaries
   p->electrodes_ready = true;
@@ -1252,153 +1257,201 @@ struct msfv_server {
     const double* v = nullptr;
     double* d = nullptr;
     double* g = nullptr;
+    long long bytes = 0;                 // admission estimate of the request
+    hipEvent_t ev_ready = nullptr;       // recorded on the caller's stream at submission
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;  // timing, on the job's stream
     std::chrono::steady_clock::time_point t_submit, t_done;
-    hipEvent_t ev = nullptr;
+    double dev_start_ms = 0.0, dev_end_ms = 0.0;      // device times since the server's epoch
     int state = 0;  // 0 queued, 1 running, 2 done
+    int waiters = 0;
     msfv_status st = MSFV_OK;
     std::string err;
   };
-  std::vector<msfv_problem*> jobs;
-  std::vector<char> busy;
+  struct Job {
+    msfv_problem* p = nullptr;
+    int max_sources = 0;
+    long long resident = 0;  // device bytes the job's problem holds
+    bool busy = false;
+    long long pending = 0;   // request handed to the worker (0: none)
+    std::condition_variable cv;
+    std::thread th;
+  };
+  std::vector<std::unique_ptr<Job>> jobs;
   std::map<long long, Req> reqs;
   std::deque<long long> queue;
-  std::vector<long long> running;
-  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_sync, ev_timing;  // idle events
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread th;
+  std::condition_variable cv_done;
   bool stop = false;
   int max_inflight = 8;
+  int running = 0;
   int device = 0;
   long long next_id = 1;
+  long long budget = 0;        // bytes
+  long long resident_total = 0;
+  long long inflight_bytes = 0;
+  long long peak_committed = 0;
+  hipEvent_t epoch = nullptr;
   // statistics since the last reset
   std::vector<double> lat_ms;
-  long long failed = 0;
+  long long failed = 0, rejected = 0;
   bool have_first = false;
   std::chrono::steady_clock::time_point t_first, t_last;
 
-  void loop();
+  void worker(Job* j);
+  void dispatch_locked();
   ~msfv_server() {
     {
       std::unique_lock<std::mutex> lk(mu);
       stop = true;
     }
-    cv_work.notify_all();
-    if (th.joinable()) th.join();
-    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& j : jobs) j->cv.notify_all();
+    for (auto& j : jobs)
+      if (j->th.joinable()) j->th.join();
+    for (auto e : ev_sync) (void)hipEventDestroy(e);
+    for (auto e : ev_timing) (void)hipEventDestroy(e);
+    if (epoch) (void)hipEventDestroy(epoch);
   }
 };
 
 namespace {
 
-// Issue one request on its job's stream (dispatcher thread, lock not held).
-msfv_status serve_issue(msfv_problem* p, msfv_server::Req& r) {
+// Device bytes a problem holds (allocated capacity of every buffer).
+long long problem_bytes(const msfv_problem* p) { return (long long)p->workspace_bytes(); }
+
+// Bytes of a request beyond its job's resident state: the caller's buffers
+// (m and g: N values each; v and D: Nr * Ns each).
+long long request_bytes(const msfv_problem* p, int ns) {
+  return 16LL * p->plan.ncell + 16LL * p->rec.count * ns;
+}
+
+// Allocate a job's source-count-dependent buffers for up to max_ns sources,
+// so that requests never reallocate them (a hipFree would synchronise the
+// device, stalling every other job).
+msfv_status reserve_sources(msfv_problem* p, int max_ns) {
+  const size_t ncs = size_t(p->plan.ncoarse) * max_ns;
+  const size_t nd = size_t(std::max(1, p->rec.count)) * max_ns;
+  HIP_OK(p->d_b.alloc(ncs));
+  HIP_OK(p->d_t.alloc(ncs));
+  HIP_OK(p->d_lam.alloc(ncs));
+  HIP_OK(p->d_D.alloc(nd));
+  HIP_OK(p->d_v.alloc(nd));
+  if (coarse_multi(p)) {
+    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, max_ns) / sizeof(double) + 1));
+    if (p->flags_cap < max_ns) {
+      if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
+      p->h_flags = nullptr;
+      p->flags_cap = 0;
+      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * max_ns));
+      p->flags_cap = max_ns;
+    }
+  }
+  return MSFV_OK;
+}
+
+// Issue one request on its job's stream and wait for it (job worker thread,
+// lock not held).
+msfv_status serve_run(msfv_problem* p, msfv_server::Req& r, hipEvent_t epoch) {
   if (r.src.count != p->src.count || r.src.ptr != p->src.ptr || r.src.cell != p->src.cell ||
       r.src.val != p->src.val) {
     p->src = r.src;
     p->electrodes_ready = false;
     p->have_forward = false;
   }
-  msfv_status st = ensure_ready(p);
-  if (st == MSFV_OK) st = forward_impl(p, r.m, r.d, nullptr);
+  msfv_status st = ensure_ready(p);  // host tables of a new source set: this job's thread only
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipStreamWaitEvent(p->stream, r.ev_ready, 0));  // inputs written on the caller's stream
+  HIP_OK(hipEventRecord(r.ev_start, p->stream));
+  st = forward_impl(p, r.m, r.d, nullptr);
   if (st == MSFV_OK) st = jtv_impl(p, r.v, r.g);
-  if (st == MSFV_OK && hipEventRecord(r.ev, p->stream) != hipSuccess)
-    st = fail(MSFV_EDEVICE, "hipEventRecord failed");
-  return st;
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipEventRecord(r.ev_end, p->stream));
+  HIP_OK(hipEventSynchronize(r.ev_end));
+  float a = 0.f, b = 0.f;
+  if (hipEventElapsedTime(&a, epoch, r.ev_start) == hipSuccess &&
+      hipEventElapsedTime(&b, epoch, r.ev_end) == hipSuccess) {
+    r.dev_start_ms = a;
+    r.dev_end_ms = b;
+  }
+  return check_status(p);
 }
 
 }  // namespace
 
-void msfv_server::loop() {
-  (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
-  for (;;) {
-    // completions
-    for (size_t k = 0; k < running.size();) {
-      Req& r = reqs[running[k]];
-      const hipError_t q = hipEventQuery(r.ev);
-      if (q == hipErrorNotReady) {
-        ++k;
-        continue;
-      }
-      r.t_done = std::chrono::steady_clock::now();
-      msfv_problem* p = jobs[r.job];
-      lk.unlock();
-      msfv_status st = q == hipSuccess ? check_status(p) : fail(MSFV_EDEVICE, hipGetErrorString(q));
-      std::string err = st == MSFV_OK ? std::string() : std::string(msfv_last_error());
-      lk.lock();
-      r.st = st;
-      r.err = err;
-      r.state = 2;
-      ev_pool.push_back(r.ev);
-      r.ev = nullptr;
-      busy[r.job] = 0;
-      lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
-      if (st != MSFV_OK) ++failed;
-      t_last = r.t_done;
-      running.erase(running.begin() + long(k));
-      cv_done.notify_all();
+// Admit queued requests, first come first served: a request waits while its
+// job is busy (a job's requests share its problem state and run in order),
+// and no request is admitted past one that does not fit the memory budget,
+// so a large request is not starved by smaller ones behind it.
+void msfv_server::dispatch_locked() {
+  for (auto it = queue.begin(); it != queue.end() && running < max_inflight;) {
+    Req& r = reqs[*it];
+    Job& j = *jobs[r.job];
+    if (j.busy) {
+      ++it;
+      continue;
     }
-    // dispatch: first queued request whose job is idle
-    bool issued = false;
-    while (int(running.size()) < max_inflight) {
-      auto it = queue.begin();
-      while (it != queue.end() && busy[reqs[*it].job]) ++it;
-      if (it == queue.end()) break;
-      const long long id = *it;
-      queue.erase(it);
-      Req& r = reqs[id];
-      busy[r.job] = 1;
-      r.state = 1;
-      if (ev_pool.empty()) {
-        hipEvent_t e = nullptr;
-        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
-        ev_pool.push_back(e);
-      }
-      r.ev = ev_pool.back();
-      ev_pool.pop_back();
-      msfv_problem* p = jobs[r.job];
-      lk.unlock();
-      msfv_status st = r.ev ? serve_issue(p, r) : fail(MSFV_EDEVICE, "hipEventCreate failed");
-      std::string err = st == MSFV_OK ? std::string() : std::string(msfv_last_error());
-      lk.lock();
-      issued = true;
-      if (st != MSFV_OK) {  // not running: complete it with its error now
-        r.st = st;
-        r.err = err;
-        r.state = 2;
-        r.t_done = std::chrono::steady_clock::now();
-        if (r.ev) ev_pool.push_back(r.ev);
-        r.ev = nullptr;
-        busy[r.job] = 0;
-        lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
-        ++failed;
-        t_last = r.t_done;
-        cv_done.notify_all();
-        continue;
-      }
-      running.push_back(id);
-    }
-    if (stop && queue.empty() && running.empty()) return;
-    if (issued) continue;
-    if (running.empty())
-      cv_work.wait(lk);
-    else
-      cv_work.wait_for(lk, std::chrono::microseconds(20));
+    if (resident_total + inflight_bytes + r.bytes > budget) break;
+    inflight_bytes += r.bytes;
+    peak_committed = std::max(peak_committed, resident_total + inflight_bytes);
+    ++running;
+    j.busy = true;
+    j.pending = *it;
+    r.state = 1;
+    it = queue.erase(it);
+    j.cv.notify_one();
   }
 }
 
-msfv_status msfv_server_create(int max_inflight, msfv_server** out) {
+void msfv_server::worker(Job* j) {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    j->cv.wait(lk, [&] { return stop || j->pending != 0; });
+    if (j->pending == 0) return;  // stopping, nothing handed over
+    const long long id = j->pending;
+    Req& r = reqs[id];  // map nodes stay put; a running request is never erased
+    lk.unlock();
+    msfv_status st = serve_run(j->p, r, epoch);
+    std::string err = st == MSFV_OK ? std::string() : std::string(msfv_last_error());
+    const auto t_done = std::chrono::steady_clock::now();
+    lk.lock();
+    r.st = st;
+    r.err = std::move(err);
+    r.t_done = t_done;
+    r.state = 2;
+    ev_sync.push_back(r.ev_ready);
+    ev_timing.push_back(r.ev_start);
+    ev_timing.push_back(r.ev_end);
+    r.ev_ready = r.ev_start = r.ev_end = nullptr;
+    lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
+    if (st != MSFV_OK) ++failed;
+    t_last = r.t_done;
+    --running;
+    inflight_bytes -= r.bytes;
+    j->busy = false;
+    j->pending = 0;
+    dispatch_locked();
+    cv_done.notify_all();
+  }
+}
+
+msfv_status msfv_server_create(int max_inflight, double budget_bytes, msfv_server** out) {
   if (!out || max_inflight < 1 || max_inflight > 64) return fail(MSFV_EINVAL, "max_inflight outside [1, 64]");
   *out = nullptr;
-  msfv_server* s = new msfv_server();
+  std::unique_ptr<msfv_server> s(new msfv_server());
   s->max_inflight = max_inflight;
-  if (hipGetDevice(&s->device) != hipSuccess) {
-    delete s;
-    return fail(MSFV_EDEVICE, "hipGetDevice failed");
+  HIP_OK(hipGetDevice(&s->device));
+  if (budget_bytes > 0) {
+    s->budget = (long long)budget_bytes;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &total_b));
+    s->budget = (long long)total_b;
   }
-  s->th = std::thread([s] { s->loop(); });
-  *out = s;
+  HIP_OK(hipEventCreate(&s->epoch));
+  HIP_OK(hipEventRecord(s->epoch, nullptr));
+  HIP_OK(hipEventSynchronize(s->epoch));
+  *out = s.release();
   return MSFV_OK;
 }
 
@@ -1408,28 +1461,66 @@ void msfv_server_destroy(msfv_server* s) {
   delete s;
 }
 
-msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int* job) {
+msfv_status msfv_server_add_job(msfv_server* s, msfv_problem* p, int max_sources, int* job) {
   if (!s || !p || !job) return fail(MSFV_EINVAL, "null argument");
-  std::unique_lock<std::mutex> lk(s->mu);
-  for (msfv_problem* q : s->jobs)
-    if (q == p) return fail(MSFV_EINVAL, "problem already registered");
+  if (max_sources < 1) return fail(MSFV_EINVAL, "max_sources must be at least 1");
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (auto& j : s->jobs)
+      if (j->p == p) return fail(MSFV_EINVAL, "problem already registered");
+  }
   if (p->rec.count <= 0) return fail(MSFV_ESTATE, "job problem has no receivers");
-  s->jobs.push_back(p);
-  s->busy.push_back(0);
+  HIP_OK(hipStreamSynchronize(p->stream));
+  {
+    // estimate before reserving: the coarse vectors (3 Nc) and data buffers
+    // (2 Nr) of max_sources sources on top of what the problem holds now
+    const long long est = problem_bytes(p) + 8LL * (3LL * p->plan.ncoarse + 2LL * p->rec.count) * max_sources;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->resident_total + est > s->budget)
+      return fail(MSFV_ENOMEM, "the job's resident state exceeds the server's memory budget");
+  }
+  msfv_status st = reserve_sources(p, max_sources);
+  if (st != MSFV_OK) return st;
+  std::unique_ptr<msfv_server::Job> j(new msfv_server::Job());
+  j->p = p;
+  j->max_sources = max_sources;
+  j->resident = problem_bytes(p);
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->resident_total + j->resident > s->budget)
+    return fail(MSFV_ENOMEM, "the job's resident state exceeds the server's memory budget");
+  s->resident_total += j->resident;
+  msfv_server::Job* raw = j.get();
+  s->jobs.push_back(std::move(j));
+  raw->th = std::thread([s, raw] { s->worker(raw); });
   *job = int(s->jobs.size()) - 1;
+  return MSFV_OK;
+}
+
+msfv_status msfv_server_request_bytes(msfv_server* s, int job, int ns, long long* resident,
+                                      long long* request) {
+  if (!s) return fail(MSFV_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (job < 0 || job >= int(s->jobs.size())) return fail(MSFV_EINVAL, "unknown job");
+  const msfv_server::Job& j = *s->jobs[job];
+  if (resident) *resident = j.resident;
+  if (request) *request = request_bytes(j.p, ns);
   return MSFV_OK;
 }
 
 msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, const int* cell,
                                const double* val, const double* m, const double* v, double* d_out,
-                               double* g_out, long long* req) {
+                               double* g_out, void* caller_stream, long long* req) {
   if (!s || !m || !v || !d_out || !g_out || !req) return fail(MSFV_EINVAL, "null argument");
   msfv_problem* p = nullptr;
+  int max_sources = 0;
   {
     std::unique_lock<std::mutex> lk(s->mu);
     if (job < 0 || job >= int(s->jobs.size())) return fail(MSFV_EINVAL, "unknown job");
-    p = s->jobs[job];
+    p = s->jobs[job]->p;
+    max_sources = s->jobs[job]->max_sources;
   }
+  if (ns < 1 || ns > max_sources)
+    return fail(MSFV_EINVAL, "request source count outside [1, the job's max_sources]");
   msfv_server::Req r;
   msfv_status st = check_columns(p, ns, ptr, cell, val, &r.src);
   if (st != MSFV_OK) return st;
@@ -1438,6 +1529,39 @@ msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, 
   r.v = v;
   r.d = d_out;
   r.g = g_out;
+  r.bytes = request_bytes(p, ns);
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->resident_total + r.bytes > s->budget) {
+      ++s->rejected;
+      return fail(MSFV_ENOMEM, "the request does not fit the server's memory budget even alone");
+    }
+    if (!s->ev_sync.empty()) {
+      r.ev_ready = s->ev_sync.back();
+      s->ev_sync.pop_back();
+    }
+    for (hipEvent_t* e : {&r.ev_start, &r.ev_end})
+      if (!s->ev_timing.empty()) {
+        *e = s->ev_timing.back();
+        s->ev_timing.pop_back();
+      }
+  }
+  auto give_back = [&]() {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (r.ev_ready) s->ev_sync.push_back(r.ev_ready);
+    if (r.ev_start) s->ev_timing.push_back(r.ev_start);
+    if (r.ev_end) s->ev_timing.push_back(r.ev_end);
+  };
+  hipError_t e = hipSuccess;
+  if (!r.ev_ready) e = hipEventCreateWithFlags(&r.ev_ready, hipEventDisableTiming);
+  if (e == hipSuccess && !r.ev_start) e = hipEventCreate(&r.ev_start);
+  if (e == hipSuccess && !r.ev_end) e = hipEventCreate(&r.ev_end);
+  // the request's inputs are ordered after the caller's work on its stream
+  if (e == hipSuccess) e = hipEventRecord(r.ev_ready, static_cast<hipStream_t>(caller_stream));
+  if (e != hipSuccess) {
+    give_back();
+    return fail(MSFV_EDEVICE, std::string("msfv_server_submit: ") + hipGetErrorString(e));
+  }
   r.t_submit = std::chrono::steady_clock::now();
   {
     std::unique_lock<std::mutex> lk(s->mu);
@@ -1449,22 +1573,27 @@ msfv_status msfv_server_submit(msfv_server* s, int job, int ns, const int* ptr, 
     s->reqs.emplace(id, std::move(r));
     s->queue.push_back(id);
     *req = id;
+    s->dispatch_locked();
   }
-  s->cv_work.notify_all();
   return MSFV_OK;
 }
 
-msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms) {
+msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms, double* dev_start_ms,
+                             double* dev_end_ms) {
   if (!s) return fail(MSFV_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(req);
   if (it == s->reqs.end()) return fail(MSFV_EINVAL, "unknown request");
-  s->cv_done.wait(lk, [&] { return it->second.state == 2; });
-  const msfv_status st = it->second.st;
-  const std::string err = it->second.err;
-  if (latency_ms)
-    *latency_ms = std::chrono::duration<double, std::milli>(it->second.t_done - it->second.t_submit).count();
-  s->reqs.erase(it);
+  ++it->second.waiters;  // keeps the entry until this waiter has read it
+  s->cv_done.wait(lk, [&] { return s->reqs.find(req)->second.state == 2; });
+  it = s->reqs.find(req);
+  msfv_server::Req& r = it->second;
+  const msfv_status st = r.st;
+  const std::string err = r.err;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+  if (dev_start_ms) *dev_start_ms = r.dev_start_ms;
+  if (dev_end_ms) *dev_end_ms = r.dev_end_ms;
+  if (--r.waiters == 0) s->reqs.erase(it);
   lk.unlock();
   if (st != MSFV_OK) return fail(st, err);
   return MSFV_OK;
@@ -1473,10 +1602,10 @@ msfv_status msfv_server_wait(msfv_server* s, long long req, double* latency_ms) 
 msfv_status msfv_server_drain(msfv_server* s) {
   if (!s) return fail(MSFV_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->running.empty(); });
+  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->running == 0; });
   // forget completed requests nobody waits for
   for (auto it = s->reqs.begin(); it != s->reqs.end();)
-    it = it->second.state == 2 ? s->reqs.erase(it) : std::next(it);
+    it = (it->second.state == 2 && it->second.waiters == 0) ? s->reqs.erase(it) : std::next(it);
   return MSFV_OK;
 }
 
@@ -1506,10 +1635,16 @@ msfv_status msfv_server_stats(msfv_server* s, msfv_serve_stats* out, int reset) 
     out->span_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
     out->throughput = out->span_s > 0 ? double(v.size()) / out->span_s : 0.0;
   }
+  out->rejected = s->rejected;
+  out->budget_bytes = double(s->budget);
+  out->resident_bytes = double(s->resident_total);
+  out->peak_committed_bytes = double(s->peak_committed);
   if (reset) {
     s->lat_ms.clear();
     s->failed = 0;
+    s->rejected = 0;
     s->have_first = false;
+    s->peak_committed = s->resident_total + s->inflight_bytes;
   }
   return MSFV_OK;
 }

@@ -6,6 +6,7 @@ changes and autotuning do not change results."""
 import numpy as np
 import pytest
 
+import _parity as PT
 import workloads as W
 from oracle import Geometry
 from oracle import reduced as R
@@ -20,11 +21,6 @@ SHAPES = [((13, 11, 9), (4, 4, 4), 3, "twolevel"),
           ((32, 32), (4, 4), 2, "multi"),               # 2-D
           ((17, 9, 12), (8, 3, 4), 5, "multi"),
           ((24, 22, 20), (8, 8, 8), 1, "twolevel")]
-
-
-def _rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 @pytest.fixture(scope="module")
@@ -63,8 +59,8 @@ def test_batch_matches_oracle_and_eager(batch_setup):
         geo = Geometry(inst.n, inst.r)
         st = R.forward(geo, inst.m, inst.sources, inst.receivers)
         g_ref = R.jtv(st, vs[k].cpu().numpy().T)
-        assert _rel(D[k].cpu().numpy(), st.D.T) < 1e-10, k
-        assert _rel(g[k].cpu().numpy(), g_ref) < 1e-8, k
+        PT.rows(D[k].cpu().numpy(), st.D.T, 1e-10, f"D of instance {k}")
+        PT.vector(g[k].cpu().numpy(), g_ref, 1e-8, f"g of instance {k}")
         assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), k
 
 
@@ -152,6 +148,39 @@ def test_batch_error_from_a_polled_problem():
     assert e.value.status == _lib.MSFV_ENOCONV
     for k in (0, 2):
         assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), k
+    b.close()
+    for p in probs:
+        p.close()
+
+
+def test_batch_after_a_source_change():
+    """A problem's source set changes between two batch calls: the batch's
+    data buffer follows the new source count, and both calls match the
+    problems' eager results."""
+    import torch
+    import paper_1707_07598_amd as msfv
+    specs = [((13, 11, 9), (4, 4, 4), 2), ((24, 22, 20), (8, 8, 8), 3)]
+    probs, ms, insts = [], [], []
+    for k, (n, r, ns) in enumerate(specs):
+        inst = W.small_instance(n, r, seed=120 + k, ns=ns, nr=6)
+        p = msfv.Problem(n, r, "reduced")
+        p.set_sources(inst.sources)
+        p.set_receivers(inst.receivers)
+        probs.append(p)
+        insts.append(inst)
+        ms.append(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
+    b = msfv.Batch(probs)
+    for ns_new in (None, 5, 1):
+        if ns_new is not None:
+            probs[1].set_sources(W.surface_dipoles(insts[1].n, ns_new))
+        vs = [torch.tensor(np.random.default_rng(130 + p.ns).standard_normal((p.ns, p.nr)), device="cuda")
+              for p in probs]
+        D, g = b.forward_jtv(ms, vs)
+        for k, p in enumerate(probs):
+            assert D[k].shape == (p.ns, p.nr)
+            Dk = p.forward(ms[k]).clone()
+            gk = p.jtv(vs[k]).clone()
+            assert torch.equal(D[k], Dk) and torch.equal(g[k], gk), (ns_new, k)
     b.close()
     for p in probs:
         p.close()
