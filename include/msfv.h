@@ -171,6 +171,25 @@ msfv_status msfv_jtv_fixed(msfv_problem* p, const double* v, double* g_out);
 msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_obs,
                              double* phi_out, double* g_out);
 
+/* msfv_misfit_grad without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as msfv_misfit_grad;
+ * the data D and the residual D - d_obs live in a fixed library-owned device
+ * array of 2^17 doubles (1 MiB per device, held until the process ends)
+ * instead of the problem's buffers.
+ *   - Nr * Ns above 65536 returns MSFV_EINVAL.
+ *   - The problem's electrode tables and coarse vectors must already exist:
+ *     after msfv_set_sources / msfv_set_receivers, run msfv_forward or
+ *     msfv_misfit_grad once first; otherwise MSFV_ESTATE.
+ *   - Stage profiling events are not recorded for this call.
+ *   - Every call on one device shares that array: calls on one device whose
+ *     executions overlap (different streams, or different problems on
+ *     streams that are not ordered) race on it and must be serialised by
+ *     the caller.  Every value read from the array is written earlier in the
+ *     same call, so nothing carries over between calls. */
+msfv_status msfv_misfit_grad_noalloc(msfv_problem* p, const double* m, const double* d_obs,
+                                     double* phi_out, double* g_out);
+
 /* Wait for the problem's stream; returns MSFV_ENONFINITE / MSFV_ENOCONV if
  * the last forward or jtv recorded that condition, else MSFV_OK. */
 msfv_status msfv_sync(msfv_problem* p);

@@ -203,6 +203,25 @@ class Problem:
             self.sync()
         return phi, g
 
+    def misfit_grad_noalloc(self, m, d_obs, phi, g, sync: bool = True):
+        """``misfit_grad`` into caller-allocated ``phi`` (1 value) and ``g``
+        (N values) through the library's allocation-free entry point: the
+        residual lives in a fixed device array (Nr * Ns <= 65536), and the
+        problem must have run a forward since its sources or receivers were
+        set."""
+        ncell = int(np.prod(self.n))
+        self._check_tensor(m, ncell, "m")
+        self._check_tensor(d_obs, self._ns * self._nr, "d_obs")
+        self._check_tensor(phi, 1, "phi")
+        self._check_tensor(g, ncell, "g")
+        _lib.check(self.lib.msfv_misfit_grad_noalloc(self._h, _dptr(m), _dptr(d_obs), _dptr(phi), _dptr(g)),
+                   "msfv_misfit_grad_noalloc")
+        self.generation += 1
+        self.last_m = m
+        if sync:
+            self.sync()
+        return phi, g
+
     def sync(self) -> None:
         _lib.check(self.lib.msfv_sync(self._h), "msfv_sync")
 

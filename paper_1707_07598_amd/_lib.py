@@ -84,6 +84,7 @@ SIGNATURES = {
     "msfv_forward": (_I, [_P, _P, _P, _P]),
     "msfv_jtv": (_I, [_P, _P, _P]),
     "msfv_misfit_grad": (_I, [_P, _P, _P, _P, _P]),
+    "msfv_misfit_grad_noalloc": (_I, [_P, _P, _P, _P, _P]),
     "msfv_jvp": (_I, [_P, _P, _P]),
     "msfv_jvp_fixed": (_I, [_P, _P, _P]),
     "msfv_jtv_fixed": (_I, [_P, _P, _P]),

@@ -671,6 +671,35 @@ msfv_status jtv_fixed_impl(msfv_problem* p, const double* v, double* g_out) {
   return MSFV_OK;
 }
 
+// Residual scratch of the allocation-free misfit entry point: the data D and
+// the residual v = D - d_obs of one call (2 Nr Ns doubles), in a fixed
+// device array instead of the problem's buffers.  Host code never passes the
+// array's name to a kernel or a copy: it uses the device address returned by
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t kScratchDoubles = size_t(1) << 17;  // 1 MiB: Nr * Ns <= 65536
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kScratchDevices] = {};
+
+// Device address of ``scratch`` on the current device.
+msfv_status scratch_address(double** out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(MSFV_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MSFV_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return MSFV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -875,6 +904,36 @@ msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_o
   const long long n = (long long)p->rec.count * p->src.count;
   STAGE(MSFV_STAGE_RESIDUAL, msfv::launch_residual(p->d_D.ptr, d_obs, p->d_v.ptr, n, phi_out, p->stream));
   return jtv_impl(p, p->d_v.ptr, g_out);
+}
+
+msfv_status msfv_misfit_grad_noalloc(msfv_problem* p, const double* m, const double* d_obs,
+                                     double* phi_out, double* g_out) {
+  if (!p || !m || !d_obs || !phi_out || !g_out) return fail(MSFV_EINVAL, "null argument");
+  const long long n = (long long)p->rec.count * p->src.count;
+  if (2 * n > (long long)kScratchDoubles)
+    return fail(MSFV_EINVAL, "msfv_misfit_grad_noalloc: Nr * Ns = " + std::to_string(n) +
+                                 " exceeds the scratch maximum of " + std::to_string(kScratchDoubles / 2));
+  if (p->src.count <= 0 || p->rec.count <= 0) return fail(MSFV_ESTATE, "no sources or receivers set");
+  // the electrode tables and coarse vectors are (re)allocated by the first
+  // forward after the sources or receivers change; this entry point does not
+  if (!p->electrodes_ready)
+    return fail(MSFV_ESTATE, "msfv_misfit_grad_noalloc: run msfv_forward or msfv_misfit_grad once after "
+                             "setting the sources and receivers");
+  double* sc = nullptr;
+  msfv_status st = scratch_address(&sc);
+  if (st != MSFV_OK) return st;
+  double* D = sc;
+  double* v = sc + n;
+  const bool prof = p->prof.on;  // stage events may create HIP events: off for this call
+  p->prof.on = false;
+  st = forward_impl(p, m, D, nullptr);
+  if (st == MSFV_OK) {
+    const hipError_t e = msfv::launch_residual(D, d_obs, v, n, phi_out, p->stream);
+    st = e == hipSuccess ? MSFV_OK : fail(MSFV_EDEVICE, std::string("launch_residual: ") + hipGetErrorString(e));
+  }
+  if (st == MSFV_OK) st = jtv_impl(p, v, g_out);
+  p->prof.on = prof;
+  return st;
 }
 
 namespace {
