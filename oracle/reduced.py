@@ -92,10 +92,16 @@ class ReducedState:
     D: np.ndarray   # Nr x Ns
 
 
-def forward(geom: Geometry, m: np.ndarray, sources, receivers, mode: str = "reduced") -> ReducedState:
-    """F_k(m) = Rx^T S_k A_k^{-1} S_k^T Q (eq. fwdProbRed)."""
+def forward(geom: Geometry, m: np.ndarray, sources, receivers, mode: str = "reduced",
+            basis: Optional[Basis] = None) -> ReducedState:
+    """F_k(m) = Rx^T S_k A_k^{-1} S_k^T Q (eq. fwdProbRed).
+
+    With ``basis`` given (a basis built at another model m0), the basis is
+    held fixed and only A_k(m) = S_k(m0)^T A(m) S_k(m0) is rebuilt: the
+    fixed-basis surrogate of eq. optredfixed, whose exact sensitivities are
+    those of eq. senssimple (``jvp_fixed``, ``jtv_fixed``)."""
     m = np.asarray(m, dtype=np.float64)
-    bas = build_basis(geom, m, mode)
+    bas = build_basis(geom, m, mode) if basis is None else basis
     A = fine_operator(geom, m)
     P = bas.csr()
     K = coarse_operator(P, A)

@@ -15,6 +15,9 @@
   fixed-basis forms (eq. senssimple) by dot test; in Lagrange mode with
   every electrode and receiver on the coarse skeleton the adaptive and
   fixed-basis gradients coincide (Y_k vanishes there and S^T A Y_k = 0).
+* The fixed-basis surrogate (eq. optredfixed: S_k(m0) held, A_k(m)
+  rebuilt) equals the adaptive model at m0, its eq. senssimple derivatives
+  match central differences of the surrogate, and its A_k scales with e^c.
 """
 import math
 
@@ -204,3 +207,36 @@ def test_uniform_perturbation_adaptive_equals_fixed(n, r):
     ja, jx = R.jvp(st, dm), R.jvp_fixed(st, dm)
     assert np.allclose(ja, jx, rtol=1e-10, atol=1e-14 * np.abs(ja).max())
     assert np.allclose(ja, 0.001 * st.D, rtol=1e-8, atol=1e-12 * np.abs(st.D).max())
+
+
+@pytest.mark.parametrize("n,r", GRIDS)
+@pytest.mark.parametrize("mode", MODES)
+def test_frozen_basis_surrogate(n, r, mode):
+    """The fixed-basis surrogate of eq. optredfixed (S_k(m0) held, A_k(m)
+    rebuilt): at m = m0 it is the adaptive forward; its exact derivative is
+    eq. senssimple with the frozen basis (jvp_fixed against central
+    differences of the frozen forward, jtv_fixed by the dot test); and the
+    frozen A_k is homogeneous of degree one in e^m."""
+    g = Geometry(n, r)
+    inst = _instance(n, r)
+    rng = np.random.default_rng(14)
+    st0 = R.forward(g, inst.m, inst.sources, inst.receivers, mode)
+    m1 = inst.m + 0.3 * rng.standard_normal(g.ncell)
+    fr = R.forward(g, m1, inst.sources, inst.receivers, mode, basis=st0.basis)
+    same = R.forward(g, inst.m, inst.sources, inst.receivers, mode, basis=st0.basis)
+    np.testing.assert_array_equal(same.D, st0.D)
+    np.testing.assert_array_equal(fr.P.toarray(), st0.P.toarray())
+    # an adaptive forward at m1 moves the basis (reduced boundaries or not,
+    # the block interiors depend on m), so the two models differ there
+    ad = R.forward(g, m1, inst.sources, inst.receivers, mode)
+    assert np.abs(ad.D - fr.D).max() > 1e-8 * np.abs(ad.D).max()
+    dm = rng.standard_normal(g.ncell)
+    eps = 1e-5
+    fd = (R.forward(g, m1 + eps * dm, inst.sources, inst.receivers, mode, basis=st0.basis).D
+          - R.forward(g, m1 - eps * dm, inst.sources, inst.receivers, mode, basis=st0.basis).D) / (2 * eps)
+    jv = R.jvp_fixed(fr, dm)
+    assert np.linalg.norm(jv - fd) <= 1e-5 * np.linalg.norm(fd)
+    V = rng.standard_normal(fr.D.shape)
+    assert abs(np.sum(jv * V) - R.jtv_fixed(fr, V) @ dm) <= 1e-12 * max(1.0, abs(np.sum(jv * V)))
+    sc = R.forward(g, m1 + 0.7, inst.sources, inst.receivers, mode, basis=st0.basis)
+    np.testing.assert_allclose(sc.K, math.exp(0.7) * fr.K, rtol=1e-12, atol=1e-14 * np.abs(fr.K).max())
