@@ -109,6 +109,8 @@ typedef struct {
   int nface;           /* face entities (3-D)                                */
   int nedge;           /* edge entities                                      */
   long long workspace_bytes; /* device bytes held by the problem             */
+  long long pairs_block; /* (own cell, corner) pairs of the dual-block solves */
+  long long pairs_face;  /* the same for the faces (3-D) or 2-D blocks      */
 } msfv_sizes;
 
 typedef struct {
@@ -165,6 +167,22 @@ msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out);
  * workspace of 2 N Ns doubles (allocated on first use). */
 msfv_status msfv_jvp_fixed(msfv_problem* p, const double* dm, double* dd_out);
 msfv_status msfv_jtv_fixed(msfv_problem* p, const double* v, double* g_out);
+
+/* Adaptive or frozen basis (Sec. 3.1, eq. optredadapt against the
+ * fixed-basis surrogate of eq. optredfixed).
+ *   MSFV_BASIS_ADAPTIVE (the default): every forward rebuilds S_k(m).
+ *   MSFV_BASIS_FROZEN  : later forwards keep the S_k of the last forward
+ *                        (the basis of the model m0 it ran at) and rebuild
+ *                        only A_k(m) = S_k(m0)^T A(m) S_k(m0); msfv_jtv,
+ *                        msfv_jvp and msfv_misfit_grad then return the exact
+ *                        sensitivities of that surrogate, eq. senssimple with
+ *                        the frozen basis (the same as msfv_jtv_fixed /
+ *                        msfv_jvp_fixed).  Needs a forward first (MSFV_ESTATE
+ *                        otherwise); allocates the fixed-basis workspace
+ *                        (2 N Ns doubles) and synchronises the stream.
+ * Switching back to MSFV_BASIS_ADAPTIVE makes the next forward rebuild S_k. */
+enum { MSFV_BASIS_ADAPTIVE = 0, MSFV_BASIS_FROZEN = 1 };
+msfv_status msfv_set_basis(msfv_problem* p, int mode);
 
 /* Misfit phi = 1/2 ||D(m) - d_obs||_F^2 (Sec. 2.2) and its gradient
  * J_k^T (D - d_obs): forward + jtv.  phi_out: device, 1 value. */

@@ -91,6 +91,7 @@ class Problem:
                                             ctypes.byref(handle)), "msfv_create")
         self._h = handle
         self.generation = 0
+        self.frozen = False
         self.last_m = None
         self._ns = 0
         self._nr = 0
@@ -176,6 +177,14 @@ class Problem:
         if sync:
             self.sync()
         return dd
+
+    def freeze_basis(self, frozen: bool = True) -> None:
+        """Keep the basis S_k of the last forward for the following forwards
+        (only A_k(m) is rebuilt; eq. optredfixed), whose J^T v and J dm are
+        then the fixed-basis sensitivities of eq. senssimple; ``False``
+        returns to rebuilding S_k(m) at every forward."""
+        _lib.check(self.lib.msfv_set_basis(self._h, 1 if frozen else 0), "msfv_set_basis")
+        self.frozen = bool(frozen)
 
     def jtv_fixed(self, v, out=None, sync: bool = True):
         """g = J_k^T v with the basis S_k held fixed, at the m of the last forward."""

@@ -44,7 +44,8 @@ class MsfvSizes(ctypes.Structure):
                 ("nnz_p", ctypes.c_longlong), ("nnz_k", ctypes.c_longlong),
                 ("nsrc", ctypes.c_int), ("nrec", ctypes.c_int), ("nblock", ctypes.c_int),
                 ("nface", ctypes.c_int), ("nedge", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_longlong)]
+                ("workspace_bytes", ctypes.c_longlong), ("pairs_block", ctypes.c_longlong),
+                ("pairs_face", ctypes.c_longlong)]
 
 
 class MsfvServeStats(ctypes.Structure):
@@ -88,6 +89,7 @@ SIGNATURES = {
     "msfv_jvp": (_I, [_P, _P, _P]),
     "msfv_jvp_fixed": (_I, [_P, _P, _P]),
     "msfv_jtv_fixed": (_I, [_P, _P, _P]),
+    "msfv_set_basis": (_I, [_P, _I]),
     "msfv_sync": (_I, [_P]),
     "msfv_get_sizes": (_I, [_P, ctypes.POINTER(MsfvSizes)]),
     "msfv_get_prolongation": (_I, [_P, _IP, _IP, _DP]),

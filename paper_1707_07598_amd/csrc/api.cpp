@@ -110,13 +110,16 @@ struct msfv_problem {
   Columns src, rec;
   bool electrodes_ready = false;
   bool have_forward = false;
+  bool basis_ready = false;  // S_k holds the basis of some model (a forward has run)
+  bool frozen = false;       // forwards keep S_k and rebuild A_k(m) only
   unsigned long long generation = 0;  // bumped whenever device buffers are (re)allocated
 
   // plan on the device
   DevBuf<msfv::EntDesc> d_edges, d_faces, d_blocks;
   DevBuf<int> d_prow, d_pcol, d_krow, d_kcol, d_kcptr, d_kcidx, d_kdslot, d_vrows;
   DevBuf<double> d_pval, d_kval, d_kdia, d_kent, d_inbuf, d_W;
-  DevBuf<double> d_m;  // copy of the m of the last forward
+  DevBuf<double> d_m;    // copy of the m of the last forward
+  DevBuf<double> d_sig;  // exp of it
   DevBuf<int> d_status;
 
   // sources / receivers / electrodes
@@ -143,6 +146,10 @@ struct msfv_problem {
   DevBuf<double> d_einv;
   DevBuf<int> d_arows;
   DevBuf<double> d_mu;  // adjoint local solutions of the wave kernels (per entity 8 x nu)
+  // dual blocks split for launching: the full blocks of full_u^3 own cells
+  // (geometry fixed at compile time) first, then the others
+  DevBuf<int> d_blist;
+  int full_u = 0, nfull = 0, nrest = 0;
   // sensitivity passes (allocated on first use)
   DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
   DevBuf<int> d_ccptr, d_ccidx, d_cccell;  // column lists of S_k
@@ -160,7 +167,7 @@ struct msfv_problem {
            d_krow.bytes() + d_kcol.bytes() + d_kcptr.bytes() + d_kcidx.bytes() + d_kdslot.bytes() +
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
-           d_m.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
+           d_m.bytes() + d_sig.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
            d_sload.bytes() + d_einv.bytes() + d_arows.bytes() + d_cg_ws.bytes() + d_mu.bytes() + d_dpval.bytes() +
            d_dkent.bytes() + d_dkval.bytes() + d_dkdia.bytes() + d_dt.bytes() + d_fu.bytes() +
            d_fz.bytes() + d_ccptr.bytes() + d_ccidx.bytes() + d_cccell.bytes();
@@ -341,7 +348,7 @@ msfv_status build_electrodes(msfv_problem* p) {
   HIP_OK(p->d_rval.upload(p->rec.val.empty() ? std::vector<double>{0.0} : p->rec.val, s));
   // coarse vectors
   const size_t ncs = size_t(nc) * std::max(1, ns);
-  HIP_OK(p->d_b.alloc(ncs));
+  HIP_OK(p->d_b.alloc(size_t(nc) * msfv::prolong_ldt(ns)));  // also the prolongation's scratch
   HIP_OK(p->d_t.alloc(ncs));
   HIP_OK(p->d_lam.alloc(ncs));
   HIP_OK(p->d_D.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
@@ -366,6 +373,7 @@ msfv::LocalParams base_params(msfv_problem* p) {
   msfv::LocalParams lp;
   lp.g = p->g;
   lp.m = p->d_m.ptr;
+  lp.sig = p->d_sig.ptr;
   lp.prow = p->d_prow.ptr;
   lp.pcol = p->d_pcol.ptr;
   lp.pval = p->d_pval.ptr;
@@ -416,6 +424,25 @@ hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned 
                                  p->d_status.ptr, work, s);
 }
 
+// Local solves of the dual blocks: the full blocks through the kernels
+// specialised for their shape, the others through the general ones.
+hipError_t launch_blocks(msfv_problem* p, const msfv::LocalParams& lp, bool adj, hipStream_t s) {
+  if (p->nfull > 0) {
+    msfv::LocalParams f = lp;
+    f.ent_list = p->d_blist.ptr;
+    f.nent = p->nfull;
+    const hipError_t e = msfv::launch_wave_full(f, p->full_u, adj, s);
+    if (e != hipSuccess) return e;
+  }
+  if (p->nrest > 0) {
+    msfv::LocalParams r = lp;
+    r.ent_list = p->d_blist.ptr + p->nfull;
+    r.nent = p->nrest;
+    return adj ? msfv::launch_local_adj(r, 0, s) : msfv::launch_local_fwd(r, 0, s);
+  }
+  return hipSuccess;
+}
+
 msfv_status ensure_ready(msfv_problem* p) {
   if (p->src.count <= 0) return fail(MSFV_ESTATE, "no sources set");
   if (p->rec.count <= 0) return fail(MSFV_ESTATE, "no receivers set");
@@ -432,10 +459,27 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
   HIP_OK(msfv::launch_zero(p->d_ent_it.ptr, p->d_ent_it.bytes(), s));
   STAGE(MSFV_STAGE_COPY_M,
-        msfv::launch_copy(p->d_m.ptr, m, P.ncell, s));
-  STAGE(MSFV_STAGE_CHECK, msfv::launch_check_finite(p->d_m.ptr, P.ncell, p->d_status.ptr, s));
+        msfv::launch_prep_model(p->d_m.ptr, p->d_sig.ptr, m, P.ncell, p->d_status.ptr, s));
 
   msfv::LocalParams lp = base_params(p);
+  if (p->frozen) {
+    // fixed basis (eq. optredfixed): S_k stays, A_k(m) = S_k^T A(m) S_k from
+    // energy blocks over each entity's fluxes at the current m
+    lp.ents = p->d_edges.ptr;
+    lp.nent = int(P.edges.size());
+    lp.nc_cap = 2;
+    STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_energy_frozen(lp, s));
+    lp.ents = p->d_faces.ptr;
+    lp.nent = int(P.faces.size());
+    lp.nc_cap = P.caps_face.nc;
+    STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_energy_frozen(lp, s));
+    if (P.dim == 3) {
+      lp.ents = p->d_blocks.ptr;
+      lp.nent = int(P.blocks.size());
+      lp.nc_cap = P.caps_block.nc;
+      STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_energy_frozen(lp, s));
+    }
+  } else {
   lp.ents = p->d_edges.ptr;
   lp.nent = int(P.edges.size());
   STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
@@ -454,7 +498,8 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
     lp.nent = int(P.blocks.size());
     set_caps(lp, P.caps_block, P.max_nu_block);
     set_stats(p, lp, 0);
-    STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_local_fwd(lp, 0, s));
+    STAGE(MSFV_STAGE_BLOCK_FWD, launch_blocks(p, lp, false, s));
+  }
   }
   STAGE(MSFV_STAGE_KASSEMBLE,
         msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
@@ -478,8 +523,9 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   if (u_out)
     STAGE(MSFV_STAGE_PROLONG,
           msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns,
-                               P.ncell, u_out, s));
+                               P.ncell, u_out, p->d_b.ptr, s));
   p->have_forward = true;
+  p->basis_ready = true;
   return MSFV_OK;
 }
 
@@ -512,7 +558,7 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
     lp.push = lagrange ? 0 : 1;
     lp.solve_adj = 1;
     set_stats(p, lp, 1);
-    STAGE(MSFV_STAGE_BLOCK_ADJ, msfv::launch_local_adj(lp, 0, s));
+    STAGE(MSFV_STAGE_BLOCK_ADJ, launch_blocks(p, lp, true, s));
   }
   lp = base_params(p);
   lp.ents = p->d_faces.ptr;
@@ -529,19 +575,23 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
   lp.ents = p->d_edges.ptr;
   lp.nent = int(P.edges.size());
   STAGE(MSFV_STAGE_EDGE_ADJ, msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
-  STAGE(MSFV_STAGE_GFINAL, msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
+  STAGE(MSFV_STAGE_GFINAL, msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
   return MSFV_OK;
 }
 
 
 // ---- sensitivities: forward-mode J dm and the fixed-basis variants ----------
 
-msfv_status sens_ready(msfv_problem* p) {
-  if (!p->have_forward) return fail(MSFV_ESTATE, "sensitivity call before msfv_forward");
+msfv_status sens_ready_alloc(msfv_problem* p) {
   const msfv::Plan& P = p->plan;
   const size_t ncs = size_t(P.ncoarse) * std::max(1, p->src.count);
   HIP_OK(p->d_dt.alloc(ncs));
   return MSFV_OK;
+}
+
+msfv_status sens_ready(msfv_problem* p) {
+  if (!p->have_forward) return fail(MSFV_ESTATE, "sensitivity call before msfv_forward");
+  return sens_ready_alloc(p);
 }
 
 msfv_status fine_ready(msfv_problem* p) {
@@ -638,7 +688,7 @@ msfv_status jvp_fixed_impl(msfv_problem* p, const double* dm, double* dd_out) {
   HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
   HIP_OK(msfv::launch_check_finite(dm, P.ncell, p->d_status.ptr, s));
   HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
-                              p->d_fu.ptr, s));
+                              p->d_fu.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_dAu(p->d_m.ptr, dm, p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, s));
   HIP_OK(msfv::launch_restrict(p->d_ccptr.ptr, p->d_ccidx.ptr, p->d_cccell.ptr, p->d_pval.ptr, p->d_fz.ptr,
                                nc, ns, P.ncell, -1.0, p->d_b.ptr, s));
@@ -663,11 +713,11 @@ msfv_status jtv_fixed_impl(msfv_problem* p, const double* v, double* g_out) {
                                    nc, s));
   HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, nullptr, s));
   HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
-                              p->d_fu.ptr, s));
+                              p->d_fu.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_lam.ptr, nc, ns, P.ncell,
-                              p->d_fz.ptr, s));
+                              p->d_fz.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_wfixed(p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, p->d_W.ptr, s));
-  HIP_OK(msfv::launch_gfinal(p->d_m.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
+  HIP_OK(msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
   return MSFV_OK;
 }
 
@@ -698,6 +748,17 @@ msfv_status scratch_address(double** out) {
   }
   *out = g_scratch_dev[dev];
   return MSFV_OK;
+}
+
+// J^T v and J dm of the problem's current model: adaptive basis (Sec. 4.3)
+// or, with the basis frozen, the exact sensitivities of the fixed-basis
+// model (eq. senssimple).
+msfv_status jtv_model(msfv_problem* p, const double* v, double* g_out) {
+  return p->frozen ? jtv_fixed_impl(p, v, g_out) : jtv_impl(p, v, g_out);
+}
+
+msfv_status jvp_model(msfv_problem* p, const double* dm, double* dd_out) {
+  return p->frozen ? jvp_fixed_impl(p, dm, dd_out) : jvp_impl(p, dm, dd_out);
 }
 
 }  // namespace
@@ -808,7 +869,35 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     if (fits(P.caps_face)) mu = std::max(mu, P.faces.size() * 8 * size_t(std::max(1, P.max_nu_face)));
     HIP_OR_CLEAN(p->d_mu.alloc(std::max<size_t>(1, mu)));
   }
+  {
+    // full dual blocks: U^3 own cells, bounded by vertex planes on every axis
+    auto full_of = [](const msfv::EntDesc& E) {
+      const int U = E.uext[0];
+      if ((U != 3 && U != 7) || E.uext[1] != U || E.uext[2] != U) return 0;
+      if (E.open_mask != 7 || E.bounded_mask != 7 || E.nc != 8 || E.nu != U * U * U) return 0;
+      for (int k = 0; k < 3; ++k)
+        if (E.cext[k] != U + 2 || E.clo[k] != E.ulo[k] - 1) return 0;
+      return U;
+    };
+    int best = 0, cnt3 = 0, cnt7 = 0;
+    for (const auto& E : P.blocks) {
+      const int u = P.dim == 3 ? full_of(E) : 0;
+      cnt3 += u == 3;
+      cnt7 += u == 7;
+    }
+    best = cnt7 >= cnt3 ? (cnt7 ? 7 : 0) : 3;
+    std::vector<int> full, rest;
+    for (int i = 0; i < int(P.blocks.size()); ++i)
+      ((best && P.dim == 3 && full_of(P.blocks[i]) == best) ? full : rest).push_back(i);
+    p->full_u = full.empty() ? 0 : best;
+    p->nfull = int(full.size());
+    p->nrest = int(rest.size());
+    full.insert(full.end(), rest.begin(), rest.end());
+    if (full.empty()) full.push_back(0);
+    HIP_OR_CLEAN(p->d_blist.upload(full, s));
+  }
   HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
+  HIP_OR_CLEAN(p->d_sig.alloc(P.ncell));
   HIP_OR_CLEAN(p->d_status.alloc(msfv::kStCount));
   HIP_OR_CLEAN(p->d_work.alloc(8));
   {
@@ -876,12 +965,32 @@ msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double
 
 msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out) {
   if (!p || !v || !g_out) return fail(MSFV_EINVAL, "null argument");
-  return jtv_impl(p, v, g_out);
+  return jtv_model(p, v, g_out);
 }
 
 msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out) {
   if (!p || !dm || !dd_out) return fail(MSFV_EINVAL, "null argument");
-  return jvp_impl(p, dm, dd_out);
+  return jvp_model(p, dm, dd_out);
+}
+
+msfv_status msfv_set_basis(msfv_problem* p, int mode) {
+  if (!p) return fail(MSFV_EINVAL, "null problem");
+  if (mode != MSFV_BASIS_ADAPTIVE && mode != MSFV_BASIS_FROZEN)
+    return fail(MSFV_EINVAL, "mode must be MSFV_BASIS_ADAPTIVE or MSFV_BASIS_FROZEN");
+  if (mode == MSFV_BASIS_ADAPTIVE) {
+    p->frozen = false;
+    return MSFV_OK;
+  }
+  if (!p->basis_ready) return fail(MSFV_ESTATE, "freezing the basis needs a forward first");
+  HIP_OK(hipStreamSynchronize(p->stream));
+  // the fixed-basis sensitivities' workspace, now rather than inside a
+  // later call (which may be captured in a graph)
+  msfv_status st = fine_ready(p);
+  if (st == MSFV_OK) st = sens_ready_alloc(p);
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipStreamSynchronize(p->stream));
+  p->frozen = true;
+  return MSFV_OK;
 }
 
 msfv_status msfv_jvp_fixed(msfv_problem* p, const double* dm, double* dd_out) {
@@ -903,7 +1012,7 @@ msfv_status msfv_misfit_grad(msfv_problem* p, const double* m, const double* d_o
   if (st != MSFV_OK) return st;
   const long long n = (long long)p->rec.count * p->src.count;
   STAGE(MSFV_STAGE_RESIDUAL, msfv::launch_residual(p->d_D.ptr, d_obs, p->d_v.ptr, n, phi_out, p->stream));
-  return jtv_impl(p, p->d_v.ptr, g_out);
+  return jtv_model(p, p->d_v.ptr, g_out);
 }
 
 msfv_status msfv_misfit_grad_noalloc(msfv_problem* p, const double* m, const double* d_obs,
@@ -931,7 +1040,7 @@ msfv_status msfv_misfit_grad_noalloc(msfv_problem* p, const double* m, const dou
     const hipError_t e = msfv::launch_residual(D, d_obs, v, n, phi_out, p->stream);
     st = e == hipSuccess ? MSFV_OK : fail(MSFV_EDEVICE, std::string("launch_residual: ") + hipGetErrorString(e));
   }
-  if (st == MSFV_OK) st = jtv_impl(p, v, g_out);
+  if (st == MSFV_OK) st = jtv_model(p, v, g_out);
   p->prof.on = prof;
   return st;
 }
@@ -967,6 +1076,9 @@ msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out) {
   out->nface = P.dim == 3 ? int(P.faces.size()) : 0;
   out->nedge = int(P.edges.size());
   out->workspace_bytes = (long long)p->workspace_bytes();
+  out->pairs_block = out->pairs_face = 0;
+  for (const auto& E : P.blocks) out->pairs_block += (long long)E.nc * E.nu;
+  for (const auto& E : P.faces) out->pairs_face += (long long)E.nc * E.nu;
   return MSFV_OK;
 }
 
@@ -1107,7 +1219,7 @@ msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, do
   // the large coarse solver polls from the host, which a graph cannot hold
   if (!b->graphs || coarse_multi(p)) {
     st = forward_impl(p, m, d, nullptr);
-    if (st == MSFV_OK) st = jtv_impl(p, v, g);
+    if (st == MSFV_OK) st = jtv_model(p, v, g);
   } else {
     msfv_batch::Graph& c = b->cache[i];
     if (!c.exec || c.m != m || c.v != v || c.d != d || c.g != g || c.generation != p->generation) {
@@ -1117,7 +1229,7 @@ msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, do
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         st = forward_impl(p, m, d, nullptr);
-        if (st == MSFV_OK) st = jtv_impl(p, v, g);
+        if (st == MSFV_OK) st = jtv_model(p, v, g);
         e = hipStreamEndCapture(s, &graph);
         if (st == MSFV_OK && e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1390,7 +1502,7 @@ long long request_bytes(const msfv_problem* p, int ns) {
 msfv_status reserve_sources(msfv_problem* p, int max_ns) {
   const size_t ncs = size_t(p->plan.ncoarse) * max_ns;
   const size_t nd = size_t(std::max(1, p->rec.count)) * max_ns;
-  HIP_OK(p->d_b.alloc(ncs));
+  HIP_OK(p->d_b.alloc(size_t(p->plan.ncoarse) * msfv::prolong_ldt(max_ns)));
   HIP_OK(p->d_t.alloc(ncs));
   HIP_OK(p->d_lam.alloc(ncs));
   HIP_OK(p->d_D.alloc(nd));
@@ -1422,7 +1534,7 @@ msfv_status serve_run(msfv_problem* p, msfv_server::Req& r, hipEvent_t epoch) {
   HIP_OK(hipStreamWaitEvent(p->stream, r.ev_ready, 0));  // inputs written on the caller's stream
   HIP_OK(hipEventRecord(r.ev_start, p->stream));
   st = forward_impl(p, r.m, r.d, nullptr);
-  if (st == MSFV_OK) st = jtv_impl(p, r.v, r.g);
+  if (st == MSFV_OK) st = jtv_model(p, r.v, r.g);
   if (st != MSFV_OK) return st;
   HIP_OK(hipEventRecord(r.ev_end, p->stream));
   HIP_OK(hipEventSynchronize(r.ev_end));

@@ -431,7 +431,8 @@ template <int BLOCK, int CPT, int NCP>
 __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
-  const EntDesc& E = a.ents[blockIdx.x];
+  const int eid = ent_index(a);
+  const EntDesc& E = a.ents[eid];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
   double* redA = pb + NCP * a.nu_cap;
@@ -520,8 +521,8 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   if (threadIdx.x == 0) {
     if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
     if (a.ent_it) {
-      a.ent_it[blockIdx.x] = itmax;
-      if (a.ent_work) a.ent_work[blockIdx.x] += work;
+      a.ent_it[eid] = itmax;
+      if (a.ent_work) a.ent_work[eid] += work;
     }
   }
   __syncthreads();  // S_k rows of this entity are visible to the workgroup
@@ -589,7 +590,8 @@ template <int BLOCK, int CPT, int NCP>
 __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int NW = BLOCK / kWave;
-  const EntDesc& E = a.ents[blockIdx.x];
+  const int eid = ent_index(a);
+  const EntDesc& E = a.ents[eid];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
   double* redA = pb + NCP * a.nu_cap;
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
         }
       }
     }
-    if (threadIdx.x == 0 && a.ent_it) a.ent_it[blockIdx.x] = 0;
+    if (threadIdx.x == 0 && a.ent_it) a.ent_it[eid] = 0;
   } else if (a.solve_adj) {
     const double tol2 = a.rtol * a.rtol;
     int itmax = 0;
@@ -806,8 +808,8 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
     if (threadIdx.x == 0) {
       if (!all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
       if (a.ent_it) {
-        a.ent_it[blockIdx.x] = itmax;
-        if (a.ent_work) a.ent_work[blockIdx.x] += work;
+        a.ent_it[eid] = itmax;
+        if (a.ent_work) a.ent_work[eid] += work;
       }
     }
   }
@@ -1062,6 +1064,20 @@ __global__ void k_check_finite(const double* m, long long n, int* status) {
   if (bad) atomicOr(status + kStNonfinite, 1);
 }
 
+// The model of a call: dst = m, sig = exp(m), and the non-finite flag.
+__global__ void k_prep_model(double* __restrict__ dst, double* __restrict__ sig,
+                             const double* __restrict__ src, long long n, int* status) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = src[i];
+    dst[i] = v;
+    sig[i] = exp(v);
+    if (!isfinite(v)) bad = true;
+  }
+  if (bad) atomicOr(status + kStNonfinite, 1);
+}
+
 __global__ void k_zero_words(unsigned* p, long long n) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -1123,24 +1139,49 @@ __global__ void k_data(const int* rptr, const int* rcell, const double* rval, in
     D[size_t(j) * nr + i] = acc;
 }
 
-__global__ void k_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
-                          int nc, int ns, long long ncell, double* u) {
+// tT[v * ldt + j] = t[j * nc + v]: the coarse coefficients vertex by vertex,
+// sources contiguous (rows padded to ldt, a multiple of 4, with zeros)
+__global__ void k_transpose_t(const double* __restrict__ t, int nc, int ns, int ldt, double* __restrict__ tT) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)nc * ldt) return;
+  const int v = int(i / ldt), j = int(i % ldt);
+  tT[i] = j < ns ? t[size_t(j) * nc + v] : 0.0;
+}
+
+// u_j = S_k t_j for every source: one cell a thread, its S_k row in
+// registers; the coefficients of its corners come four sources at a time
+// from the vertex-major copy (two 16-byte loads per corner), and each
+// source's value is stored coalesced across the wave.
+__global__ __launch_bounds__(256) void k_prolong(const int* __restrict__ prow, const int* __restrict__ pcol,
+                                                 const double* __restrict__ pval, const double* __restrict__ tT,
+                                                 int ldt, int ns, long long ncell, double* __restrict__ u) {
   const long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (cell >= ncell) return;
-  const int a = prow[cell], b = prow[cell + 1];
+  const int a = prow[cell];
+  const int len = prow[cell + 1] - a;
   int col[8];
   double val[8];
-  const int len = b - a;
+#pragma unroll
   for (int q = 0; q < 8; ++q) {
     col[q] = q < len ? pcol[a + q] : 0;
     val[q] = q < len ? pval[a + q] : 0.0;
   }
-  for (int j = 0; j < ns; ++j) {
-    const double* tj = t + size_t(j) * nc;
-    double acc = 0.0;
-    for (int q = 0; q < 8; ++q)
-      if (q < len) acc += val[q] * tj[col[q]];
-    u[size_t(j) * ncell + cell] = acc;
+  for (int j0 = 0; j0 < ns; j0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < len) {
+        const double2* tp = reinterpret_cast<const double2*>(tT + size_t(col[q]) * ldt + j0);
+        const double2 lo = tp[0], hi = tp[1];
+        acc[0] += val[q] * lo.x;
+        acc[1] += val[q] * lo.y;
+        acc[2] += val[q] * hi.x;
+        acc[3] += val[q] * hi.y;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (j0 + jj < ns) u[size_t(j0 + jj) * ncell + cell] = acc[jj];
   }
 }
 
@@ -1167,21 +1208,26 @@ __global__ void k_sload(int nelec, const int* ecell, const int* rptr, const int*
   sload[e * 8 + c] = acc;
 }
 
-__global__ void k_gfinal(const double* m, const double* W, GridInfo g, long long ncell,
-                         double* grad) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= ncell) return;
-  const int x = int(i % g.n[0]);
-  const int y = int((i / g.n[0]) % g.n[1]);
-  const int z = int(i / ((long long)g.n[0] * g.n[1]));
+// g_i = sum over the fluxes f of cell i of dT_f/dm_i W_f, with sigma = exp(m)
+// precomputed: workgroups walk x-rows of cells (xb workgroups a row), so a
+// cell's coordinates come from the workgroup's row without a per-cell
+// division.
+__global__ __launch_bounds__(256) void k_gfinal(const double* __restrict__ sig, const double* __restrict__ W,
+                                                GridInfo g, long long ncell, int xb, double* __restrict__ grad) {
+  const int row = blockIdx.x / xb;
+  const int x = (blockIdx.x - row * xb) * blockDim.x + threadIdx.x;
+  if (x >= g.n[0]) return;
+  const int y = row % g.n[1], z = row / g.n[1];
+  const long long i = (long long)row * g.n[0] + x;
   const int c[3] = {x, y, z};
-  const double si = exp(m[i]);
+  const double si = sig[i];
   double acc = 0.0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int st = gstride_of(g, k);
     const double* Wk = W + k * ncell;
-    if (c[k] + 1 < g.n[k]) acc += dharm(si, exp(m[i + st])) * Wk[i];
-    if (c[k] > 0) acc += dharm(si, exp(m[i - st])) * Wk[i - st];
+    if (c[k] + 1 < g.n[k]) acc += dharm(si, sig[i + st]) * Wk[i];
+    if (c[k] > 0) acc += dharm(si, sig[i - st]) * Wk[i - st];
   }
   grad[i] = acc;
 }
@@ -1400,10 +1446,15 @@ hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, in
   return hipGetLastError();
 }
 
+int prolong_ldt(int ns) { return (std::max(ns, 1) + 3) / 4 * 4; }
+
 hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
-                          int nc, int ns, long long ncell, double* u, hipStream_t s) {
+                          int nc, int ns, long long ncell, double* u, double* scratch, hipStream_t s) {
+  const int ldt = prolong_ldt(ns);
+  const long long nt = (long long)nc * ldt;
+  hipLaunchKernelGGL(k_transpose_t, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s, t, nc, ns, ldt, scratch);
   hipLaunchKernelGGL(k_prolong, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, prow, pcol, pval,
-                     t, nc, ns, ncell, u);
+                     scratch, ldt, ns, ncell, u);
   return hipGetLastError();
 }
 
@@ -1418,10 +1469,20 @@ hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int*
   return hipGetLastError();
 }
 
-hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long ncell, double* grad,
+hipError_t launch_gfinal(const double* sig, const double* W, GridInfo g, long long ncell, double* grad,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_gfinal, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, m, W, g, ncell,
+  const int rows = int(ncell / g.n[0]);
+  const int xb = (g.n[0] + 255) / 256;
+  hipLaunchKernelGGL(k_gfinal, dim3(unsigned(rows) * unsigned(xb)), dim3(256), 0, s, sig, W, g, ncell, xb,
                      grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_model(double* dst, double* sig, const double* src, long long n, int* status,
+                             hipStream_t s) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_prep_model, dim3(unsigned(std::max<long long>(blocks, 1))), dim3(256), 0, s, dst, sig,
+                     src, n, status);
   return hipGetLastError();
 }
 

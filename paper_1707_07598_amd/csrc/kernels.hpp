@@ -33,6 +33,7 @@ struct LocalParams {
   const EntDesc* recv = nullptr;  // entities receiving adjoint loads (next lower kind)
   GridInfo g{};
   const double* m = nullptr;
+  const double* sig = nullptr;  // exp(m), where a kernel reads it instead of forming it
   const int* prow = nullptr;
   const int* pcol = nullptr;
   double* pval = nullptr;
@@ -66,7 +67,13 @@ struct LocalParams {
   int uni_cap = 0;                        // wave kernels: doubles of the shared plane-buffer region
   const double* dm = nullptr;             // tangent passes: direction of the model perturbation
   double* dpval = nullptr;                // tangent passes: dS_k values (CSR of S_k)
+  const int* ent_list = nullptr;          // if set: workgroup b solves entity ent_list[b] of ents
 };
+
+// The entity of this workgroup (per-entity outputs are indexed by it).
+__device__ __forceinline__ int ent_index(const LocalParams& a) {
+  return a.ent_list ? a.ent_list[blockIdx.x] : int(blockIdx.x);
+}
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s);
 hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s);
@@ -123,9 +130,16 @@ hipError_t launch_coarse_pcg_large(const double* kdia, const int ncv[3], const d
 hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double* rhs, double* x,
                              int ncol, double rtol, int maxit, const CoarseDefl* defl, int* status,
                              unsigned long long* work, hipStream_t s);
+// energy blocks of the entities of p.ents (corner count <= p.nc_cap <= 8)
+// from the S_k values in p.pval and p.sig = exp(m), into p.kent: A_k of a
+// frozen basis (wave_kernels.hip)
+hipError_t launch_energy_frozen(const LocalParams& p, hipStream_t s);
 // wave-per-corner local solves (wave_kernels.hip)
 bool wave_path_fits(const LocalParams& p);
 hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);
+// the same for full dual blocks of u^3 own cells (u = 3 or 7) listed in
+// p.ent_list, with their geometry fixed at compile time
+hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s);
 // out[slot_dst[s] + j*nc] = sum_e w[e] * pval[pidx[e]] * (colw ? colw[j*colw_ld + col[e]] : 1)
 // for slot s and column j < ncol (one thread each).
 hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,
@@ -135,14 +149,21 @@ hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const i
 hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
                        const int* prow, const int* pcol, const double* pval, const double* t,
                        int nc, double* D, hipStream_t s, int accumulate = 0);
+// u_j = S_k t_j (N values per source, column j contiguous); scratch holds
+// nc * prolong_ldt(ns) doubles (the coefficients vertex by vertex)
+int prolong_ldt(int ns);
 hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
-                          int nc, int ns, long long ncell, double* u, hipStream_t s);
+                          int nc, int ns, long long ncell, double* u, double* scratch, hipStream_t s);
 hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
                         const double* rw, const int* sptr, const int* sidx, const double* sw,
                         const int* prow, const int* pcol, const double* t, const double* lam,
                         const double* v, int nc, int ns, int nr, double* sload, hipStream_t s);
-hipError_t launch_gfinal(const double* m, const double* W, GridInfo g, long long ncell, double* grad,
+// grad from the per-flux weights W (3N) with sig = exp(m)
+hipError_t launch_gfinal(const double* sig, const double* W, GridInfo g, long long ncell, double* grad,
                          hipStream_t s);
+// dst = m, sig = exp(m), status flag for non-finite entries
+hipError_t launch_prep_model(double* dst, double* sig, const double* src, long long n, int* status,
+                             hipStream_t s);
 // Sensitivity passes (forward-mode J and the fixed-basis variants):
 // tangent edge basis and energy blocks (kent <- dK_E, dpval <- dS on own cells)
 hipError_t launch_edge_tan(const LocalParams& p, int lagrange, hipStream_t s);

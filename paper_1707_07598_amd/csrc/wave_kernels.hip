@@ -749,10 +749,8 @@ __device__ __forceinline__ int corner_in(const EntDesc& R, int vid) {
 // two blocks resident per compute unit, so one block's setup and gathers
 // overlap the other's iterations.
 template <int NWAVE, int NCMAX, int LMAX>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDesc& E, int eid, double* lds) {
   constexpr int BLOCK = NWAVE * 64;
-  const EntDesc& E = a.ents[blockIdx.x];
   const WaveLds S = carve<NWAVE, NCMAX, NWAVE>(a, lds);
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
@@ -951,8 +949,8 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
         itm = max(itm, S.wit[q]);
         wk += (unsigned long long)S.wit[q] * E.nu;
       }
-    a.ent_it[blockIdx.x] = itm;
-    if (a.ent_work) a.ent_work[blockIdx.x] += wk;
+    a.ent_it[eid] = itm;
+    if (a.ent_work) a.ent_work[eid] += wk;
   }
   // energy block K_E = sum over the touched fluxes T dphi dphi^T: one thread
   // per own cell and its owned fluxes, then a fixed-order block reduction
@@ -986,6 +984,40 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
   }
 }
 
+// A dual block of U^3 own cells bounded by vertex planes on every axis (the
+// full blocks of coarsening U + 1): the geometry fields every helper reads
+// become compile-time constants, so index arithmetic, plane offsets and
+// neighbour masks fold away; position, corners and table offsets stay the
+// entity's.
+template <int U>
+__device__ __forceinline__ EntDesc full_block(const EntDesc& src) {
+  EntDesc E = src;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    E.uext[k] = U;
+    E.cext[k] = U + 2;
+    E.clo[k] = src.ulo[k] - 1;
+  }
+  E.open_mask = 7;
+  E.bounded_mask = 7;
+  E.nc = 8;
+  E.nu = U * U * U;
+  return E;
+}
+
+// FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks.
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
+  extern __shared__ double lds[];
+  const int eid = ent_index(a);
+  if constexpr (FULLU > 0) {
+    const EntDesc E = full_block<FULLU>(a.ents[eid]);
+    wave_fwd_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
+  } else {
+    wave_fwd_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint local solves (source-reduced, transposed) of one entity per
 // workgroup, corners distributed over the waves as in the forward kernel.
@@ -993,16 +1025,14 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(L
 // basis table; each corner's adjoint solution mu_c goes to the entity's
 // slice of a global scratch (it stays in L2) for the flux weights.
 template <int NWAVE, int NCMAX, int LMAX>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDesc& E, int eid, double* lds) {
   constexpr int BLOCK = NWAVE * 64;
-  const EntDesc& E = a.ents[blockIdx.x];
   const WaveLds S = carve<NWAVE, NCMAX, NWAVE>(a, lds);
   const int nc = E.nc;
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
-  double* mus = a.mu_scratch + size_t(blockIdx.x) * NCMAX * a.nu_cap;  // mu_c on own cells
+  double* mus = a.mu_scratch + size_t(eid) * NCMAX * a.nu_cap;  // mu_c on own cells
   load_phi_table<BLOCK>(E, a, S.phi, false);
   // M_E = sum_j t_j lambda_j^T on the corners; t and lambda of the corners
   // are staged, a chunk of sources at a time, through the plane buffers
@@ -1278,8 +1308,8 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
         itm = max(itm, S.wit[q]);
         wk += (unsigned long long)S.wit[q] * E.nu;
       }
-    a.ent_it[blockIdx.x] = itm;
-    if (a.ent_work) a.ent_work[blockIdx.x] += wk;
+    a.ent_it[eid] = itm;
+    if (a.ent_work) a.ent_work[eid] += wk;
   }
   // flux weights W_f = -dphi^T M dphi - sum_c (mu_c(u) - mu_c(n)) dphi_c for
   // owned fluxes; the quadratic form uses the symmetric part of M (upper
@@ -1328,6 +1358,18 @@ __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(L
   }
 }
 
+
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
+  extern __shared__ double lds[];
+  const int eid = ent_index(a);
+  if constexpr (FULLU > 0) {
+    const EntDesc E = full_block<FULLU>(a.ents[eid]);
+    wave_adj_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
+  } else {
+    wave_adj_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Tangent of the face / dual-block basis along dm (Sec. 4.5, forward mode):
@@ -1451,12 +1493,56 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
   }
 }
 
+// Galerkin energy blocks from S_k values already in memory and sigma =
+// exp(m) of the current model: the frozen basis S_k(m0) of eq. optredfixed, with A_k(m) = S_k^T A(m)
+// S_k rebuilt (eq. reducedPDE).  Per entity, K_E = sum over the fine fluxes
+// the entity owns of T_f(m) dphi dphi^T over its corners -- the same
+// partition of the fluxes and the same sums as the energy phase of the
+// local-solve kernels, with phi read from the CSR rows (an own cell's row
+// holds the entity's corners in order; a neighbour's row is searched).
+template <int NCMAX>
+__global__ __launch_bounds__(256) void k_energy_frozen(LocalParams a) {
+  constexpr int NQ = NCMAX * (NCMAX + 1) / 2;
+  __shared__ double red[4 * NQ];
+  const EntDesc& E = a.ents[blockIdx.x];
+  const int nc = E.nc;
+  const int g0 = E.ulo[0] + a.g.s1 * E.ulo[1] + a.g.s2 * E.ulo[2];
+  double kacc[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) kacc[i] = 0.0;
+  const int nflux = owned_flux_count(E);
+  for (int item = threadIdx.x; item < nflux; item += 256) {
+    const OwnedFlux f = owned_flux(E, a.g, g0, item);
+    if (!f.valid) continue;
+    const int gn = f.gid + f.sgn * gstr(a.g, f.ax);
+    const double T = harm(a.sig[f.gid], a.sig[gn]);
+    const int r0 = a.prow[f.gid];
+    double dp[NCMAX];
+#pragma unroll
+    for (int q = 0; q < NCMAX; ++q)
+      dp[q] = q < nc ? a.pval[r0 + q] - p_lookup(a.prow, a.pcol, a.pval, gn, E.vid[q]) : 0.0;
+    int qq = 0;
+#pragma unroll
+    for (int q = 0; q < NCMAX; ++q) {
+      const double tq = T * dp[q];
+#pragma unroll
+      for (int q2 = q; q2 < NCMAX; ++q2) kacc[qq++] += tq * dp[q2];
+    }
+  }
+  block_sum<4, NQ>(kacc, red);
+  if (threadIdx.x < nc * nc) {
+    const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
+    const int lo = min(q, q2), hi = max(q, q2);
+    a.kent[E.kbase + threadIdx.x] = red[lo * NCMAX - lo * (lo - 1) / 2 + (hi - lo)];
+  }
+}
+
 template <int NWAVE, int PHIC = 8, int RED = 8>
 size_t wave_lds_bytes(const LocalParams& p) {
   return (size_t(1 + PHIC) * p.sig_cap + p.nu_cap + 128 + 40 + RED * 36 + size_t(p.uni_cap)) * sizeof(double);
 }
 
-template <int NWAVE, int NCMAX, int LMAX>
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
 hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
   LocalParams p = pin;
   // plane buffers: one a wave, or four (one a corner) for the one-wave path
@@ -1466,12 +1552,12 @@ hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (adj && !p.mu_scratch) return hipErrorInvalidValue;
   if (adj) {
-    auto kern = k_wave_adj<NWAVE, NCMAX, LMAX>;
+    auto kern = k_wave_adj<NWAVE, NCMAX, LMAX, FULLU>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
   } else {
-    auto kern = k_wave_fwd<NWAVE, NCMAX, LMAX>;
+    auto kern = k_wave_fwd<NWAVE, NCMAX, LMAX, FULLU>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
@@ -1512,6 +1598,27 @@ hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.col_cap <= 1) return launch_wave_t<4, 8, 1>(p, adj, s);
   if (p.col_cap <= 3) return launch_wave_t<4, 8, 3>(p, adj, s);
   return launch_wave_t<4, 8, 7>(p, adj, s);
+}
+
+hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (u == 7) return launch_wave_t<4, 8, 7, 7>(p, adj, s);
+  if (u == 3) return launch_wave_t<4, 8, 3, 3>(p, adj, s);
+  return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_energy_frozen(const LocalParams& p, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (p.nc_cap <= 2) {
+    hipLaunchKernelGGL(k_energy_frozen<2>, dim3(p.nent), dim3(256), 0, s, p);
+  } else if (p.nc_cap <= 4) {
+    hipLaunchKernelGGL(k_energy_frozen<4>, dim3(p.nent), dim3(256), 0, s, p);
+  } else if (p.nc_cap <= 8) {
+    hipLaunchKernelGGL(k_energy_frozen<8>, dim3(p.nent), dim3(256), 0, s, p);
+  } else {
+    return hipErrorInvalidConfiguration;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_wave_tan(const LocalParams& p, hipStream_t s) {

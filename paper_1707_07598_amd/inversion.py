@@ -7,8 +7,11 @@ subject to m_L <= m <= m_H, where D(m) is the multiscale forward model of a
 cell-centred grid.  Each Gauss-Newton step solves
     (J^T J + alpha L^T L) s = -grad phi
 on the variables that are not held at a bound, by a few conjugate-gradient
-iterations (J s and J^T w from the library: the adaptive basis by default,
-or the fixed basis), then takes a projected Armijo line search.  The driver
+iterations (J s and J^T w from the library), then takes a projected Armijo
+line search.  ``basis="adaptive"`` (eq. optredadapt) rebuilds S_k(m) at
+every forward and differentiates through it (Sec. 4.3); ``basis="fixed"``
+is the fixed-basis surrogate of eq. optredfixed: S_k is built once at the
+starting model and frozen, only A_k(m) is rebuilt, and J is eq. senssimple.  The driver
 only orchestrates: every model-dependent operation (basis, Galerkin
 operator, coarse solves, sensitivities) runs in the HIP library, and the
 vector algebra in device tensors.
@@ -82,8 +85,8 @@ def gauss_newton(prob, m0, d_obs, alpha: float, m_ref=None,
                  max_iter: int = 10, cg_iter: int = 15, cg_tol: float = 1e-2,
                  basis: str = "adaptive", max_backtrack: int = 8,
                  callback: Optional[Callable[[int, GNIteration], None]] = None):
-    """Run projected Gauss-Newton-PCG from m0; returns (m, history)."""
-    torch = _torch()
+    """Run projected Gauss-Newton-PCG from m0; returns (m, history).  The
+    problem is left with an adaptive basis."""
     if basis not in ("adaptive", "fixed"):
         raise ValueError("basis must be 'adaptive' or 'fixed'")
     fixed = basis == "fixed"
@@ -92,10 +95,23 @@ def gauss_newton(prob, m0, d_obs, alpha: float, m_ref=None,
     m = m0.clone().clamp_(lo, hi)
     m_ref = m.clone() if m_ref is None else m_ref
     history: List[GNIteration] = []
+    prob.freeze_basis(False)
     f, phi_d, phi_r, r = _objective(prob, m, d_obs, reg, alpha, m_ref)
+    if fixed:
+        prob.freeze_basis(True)  # S_k(m0) from the forward just run
+    try:
+        return _gn_loop(prob, m, d_obs, reg, alpha, m_ref, lo, hi, max_iter, cg_iter, cg_tol,
+                        max_backtrack, callback, history, f, phi_d, phi_r, r)
+    finally:
+        prob.freeze_basis(False)
+
+
+def _gn_loop(prob, m, d_obs, reg, alpha, m_ref, lo, hi, max_iter, cg_iter, cg_tol, max_backtrack,
+             callback, history, f, phi_d, phi_r, r):
+    torch = _torch()
     for it in range(max_iter):
         # gradient at the current forward state
-        gd = prob.jtv_fixed(r) if fixed else prob.jtv(r)
+        gd = prob.jtv(r)
         g = gd + alpha * reg.apply_ltl(m - m_ref)
         eps = 1e-12
         active = ((m <= lo + eps) & (g > 0)) | ((m >= hi - eps) & (g < 0))
@@ -103,8 +119,7 @@ def gauss_newton(prob, m0, d_obs, alpha: float, m_ref=None,
 
         def hess(v):
             v = v * free
-            jv = prob.jvp(v, fixed=fixed)
-            return (prob.jtv_fixed(jv) if fixed else prob.jtv(jv)) * free + alpha * reg.apply_ltl(v) * free
+            return prob.jtv(prob.jvp(v)) * free + alpha * reg.apply_ltl(v) * free
 
         # conjugate gradients on the free variables for H s = -g
         b = -g * free

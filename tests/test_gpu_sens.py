@@ -152,3 +152,64 @@ def test_fixed_versus_adaptive_two_block_model():
     assert errs["uniform"][2] < 1e-9
     assert errs["block"][0] < errs["block"][1]
     prob.close()
+
+
+FROZEN_CASES = [((13, 11, 9), (4, 4, 4)), ((17, 9, 12), (8, 3, 4)), ((40, 36, 34), (16, 16, 16)),
+                ((23, 17), (5, 6))]
+
+
+@pytest.mark.parametrize("n,r", FROZEN_CASES)
+@pytest.mark.parametrize("mode", ["reduced", "lagrange"])
+def test_frozen_basis_matches_oracle(n, r, mode):
+    """The fixed-basis surrogate (eq. optredfixed): after a forward at m0 the
+    basis is frozen; a forward at m1 keeps S_k bit for bit, rebuilds A_k(m1)
+    and gives the oracle's surrogate data and coarse coefficients; J^T v and
+    J dm are the surrogate's exact sensitivities (eq. senssimple with the
+    frozen basis); unfreezing returns to the adaptive model."""
+    import torch
+    inst = W.small_instance(n, r, seed=41, ns=3, nr=5)
+    g = Geometry(n, r)
+    rng = np.random.default_rng(42)
+    m1 = inst.m + 0.4 * rng.standard_normal(g.ncell)
+    st0 = R.forward(g, inst.m, inst.sources, inst.receivers, mode)
+    fr = R.forward(g, m1, inst.sources, inst.receivers, mode, basis=st0.basis)
+    V = rng.standard_normal(fr.D.shape)
+    dm = rng.standard_normal(g.ncell)
+    prob = _problem(n, r, mode, inst)
+    prob.forward(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
+    P0 = prob.prolongation()[2].copy()
+    prob.freeze_basis(True)
+    m1t = torch.tensor(m1, dtype=torch.float64, device="cuda")
+    D = prob.forward(m1t).cpu().numpy()
+    assert np.array_equal(prob.prolongation()[2], P0)
+    (krp, kcol, kval), t = prob.coarse()
+    import scipy.sparse as sp
+    K = sp.csr_matrix((kval, kcol, krp), shape=(g.ncoarse, g.ncoarse)).toarray()
+    PT.rows(K, fr.K, 1e-10, "A_k(m1) of the frozen basis")
+    PT.rows(t, fr.t.T, 1e-10, "t")
+    PT.rows(D, fr.D.T, 1e-10, "D")
+    gg = prob.jtv(torch.tensor(V.T.copy(), device="cuda")).cpu().numpy()
+    PT.vector(gg, R.jtv_fixed(fr, V), 1e-8, "J^T v of the frozen model")
+    PT.gradient_per_source(prob, fr, V, 1e-8, fixed=True)
+    jv = prob.jvp(torch.tensor(dm, device="cuda")).cpu().numpy()
+    PT.rows(jv, R.jvp_fixed(fr, dm).T, 1e-8, "J dm of the frozen model")
+    prob.freeze_basis(False)
+    D1 = prob.forward(m1t).cpu().numpy()
+    PT.rows(D1, R.forward(g, m1, inst.sources, inst.receivers, mode).D.T, 1e-10, "D adaptive at m1")
+    prob.close()
+
+
+def test_frozen_basis_errors():
+    import torch
+    import paper_1707_07598_amd as msfv
+    from paper_1707_07598_amd import _lib
+    inst = W.small_instance((13, 11, 9), (4, 4, 4), seed=43, ns=2, nr=3)
+    prob = _problem(inst.n, inst.r, "reduced", inst)
+    with pytest.raises(msfv.MsfvError) as e:
+        prob.freeze_basis(True)  # no basis yet
+    assert e.value.status == _lib.MSFV_ESTATE
+    prob.forward(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
+    with pytest.raises(msfv.MsfvError) as e:
+        _lib.check(prob.lib.msfv_set_basis(prob._h, 7), "msfv_set_basis")
+    assert e.value.status == _lib.MSFV_EINVAL
+    prob.close()
