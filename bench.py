@@ -449,18 +449,38 @@ def run_batch(args) -> int:
         p.sync()
 
     b = msfv.Batch(probs)
-    streams, graphs = b.autotune(ms, vs)
-    for _ in range(args.warmup):
-        b.forward_jtv(ms, vs, sync=False)
-    b.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.forward_jtv(ms, vs, sync=False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    b.sync()
+
+    def timed(steps):
+        for _ in range(args.warmup):
+            b.forward_jtv(ms, vs, sync=False)
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.forward_jtv(ms, vs, sync=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.sync()
+        return dt
+
     n = len(probs)
+    # each form at its best stream count: the per-problem path (graphs) and
+    # the shared launches of the local solves across problems
+    forms = {}
+    for name, graphs, shared in (("streams+graphs", True, 0), ("shared launches, 1 pipeline", False, 1),
+                                 ("shared launches, 2 pipelines", False, 2),
+                                 ("shared launches, 4 pipelines", False, 4)):
+        best = None
+        for sc in (4, 8, 16):
+            if sc < 2 * shared:
+                continue
+            b.set_options(sc, graphs, shared)
+            dt = timed(max(1, args.steps // 4))
+            if best is None or dt < best[0]:
+                best = (dt, sc)
+        forms[name] = {"streams": best[1], "solves_per_s": n * max(1, args.steps // 4) / best[0]}
+    streams, graphs, shared = b.autotune(ms, vs)
+    elapsed = timed(args.steps)
     value = n * args.steps / elapsed
     out = {
         "metric": "MSFV forward+J^T v solves/s, batch of mixed instances (one solve = one instance)",
@@ -471,7 +491,8 @@ def run_batch(args) -> int:
                    "fine_cells": cells, "sources": int(sum(i.sources.count for i in insts)),
                    "bc_mode": "reduced"},
         "plain_solves_per_s": n / plain_s, "speedup_vs_plain": value / (n / plain_s),
-        "autotuned": {"streams": streams, "graphs": graphs}, "setup_s": setup_s,
+        "forms": forms,
+        "autotuned": {"streams": streams, "graphs": graphs, "shared": shared}, "setup_s": setup_s,
     }
     b.close()
     for p in probs:

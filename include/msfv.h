@@ -155,9 +155,10 @@ msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out);
  * of Sec. 4.5): dD = Rx^T (dS_k t + S_k dt), A_k dt = dS_k^T q - dA_k t, where
  * dS_k is the basis tangent (the local problems differentiated along dm) and
  * dA_k the Galerkin operator's derivative.  dm: device N; dd_out: device
- * Nr*Ns (layout of D).  MSFV_ESTATE before a forward; MSFV_EINVAL for
- * coarsening above 8 (entities wider than one wavefront); MSFV_ENONFINITE
- * (via msfv_sync) if dm holds NaN or Inf. */
+ * Nr*Ns (layout of D).  Entities of any size (faces and dual blocks wider
+ * than one wavefront, coarsening above 8, run one workgroup an entity).
+ * MSFV_ESTATE before a forward; MSFV_ENONFINITE (via msfv_sync) if dm holds
+ * NaN or Inf. */
 msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out);
 
 /* The same with the basis held fixed (eq. senssimple, the "fixed" basis of
@@ -271,10 +272,29 @@ const char* msfv_stage_name(int stage);
  *                     valid after msfv_batch_sync.
  * msfv_batch_sync   : waits for the batch's work and reports the first
  *                     failing problem's status (ENOCONV, ENONFINITE).
- * msfv_batch_set_options / get_options : streams in [1, 16]; graphs 0/1.
- * msfv_batch_autotune : times one call per candidate (streams 1, 2, 4, 8,
- *                     16 capped at count; graphs on and off) with the given
- *                     buffers, keeps the fastest and reports it. */
+ * msfv_batch_set_options / get_options : streams in [1, 16]; graphs 0/1;
+ *                     shared in [0, 8].  With shared = P > 0 the local
+ *                     solves (edges, faces, dual blocks, forward and
+ *                     adjoint) run as shared launches: one launch per
+ *                     stage and kernel class over (problem, entity) items, a
+ *                     fixed grid of as many workgroups as fit the device
+ *                     striding over them (dual blocks of different problems
+ *                     fill the compute units together).  The problems are
+ *                     dealt, largest first, over P pipelines; each pipeline
+ *                     is issued by a host thread of its own, runs its shared
+ *                     launches on one pool stream and the per-problem parts
+ *                     (model copy, Galerkin assembly, coarse solves, data,
+ *                     gradient gather) of its members on further pool
+ *                     streams, so the local launches of one pipeline overlap
+ *                     the coarse solves of another.  Problems with a frozen
+ *                     basis use the per-problem path.  Graphs apply to the
+ *                     per-problem path.  set_options waits for the batch's
+ *                     work.
+ * msfv_batch_autotune : times one call per candidate (shared launches in 1,
+ *                     2 or 4 pipelines, or the per-problem path with and
+ *                     without graphs; streams 1, 2, 4, 8, 16 capped at
+ *                     count) with the given buffers, keeps the fastest and
+ *                     reports it. */
 typedef struct msfv_batch msfv_batch;
 msfv_status msfv_batch_create(int count, msfv_problem* const* problems, void* hip_stream,
                               msfv_batch** out);
@@ -282,11 +302,11 @@ void msfv_batch_destroy(msfv_batch* b);
 msfv_status msfv_batch_forward_jtv(msfv_batch* b, const double* const* m, const double* const* v,
                                    double* const* d_out, double* const* g_out);
 msfv_status msfv_batch_sync(msfv_batch* b);
-msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs);
-msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs);
+msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs, int shared);
+msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs, int* shared);
 msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const double* const* v,
                                 double* const* d_out, double* const* g_out, int* streams_out,
-                                int* graphs_out);
+                                int* graphs_out, int* shared_out);
 
 /* ---- Serving ----------------------------------------------------------------
  * A server runs forward (eq. fwdProbRed) + J_k^T v (Sec. 4.3) requests for

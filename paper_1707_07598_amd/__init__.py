@@ -412,24 +412,29 @@ class Batch:
     def sync(self):
         _lib.check(self.lib.msfv_batch_sync(self._h), "msfv_batch_sync")
 
-    def set_options(self, streams: int, graphs: bool):
-        _lib.check(self.lib.msfv_batch_set_options(self._h, int(streams), int(bool(graphs))),
+    def set_options(self, streams: int, graphs: bool, shared: int = 0):
+        """Streams of the pool, HIP graphs for the per-problem path, and the
+        number of pipelines of shared launches of the local solves across
+        problems (0: per-problem path)."""
+        _lib.check(self.lib.msfv_batch_set_options(self._h, int(streams), int(bool(graphs)), int(shared)),
                    "msfv_batch_set_options")
 
     def options(self):
-        s, g = ctypes.c_int(), ctypes.c_int()
-        _lib.check(self.lib.msfv_batch_get_options(self._h, ctypes.byref(s), ctypes.byref(g)),
+        s, g, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.msfv_batch_get_options(self._h, ctypes.byref(s), ctypes.byref(g), ctypes.byref(sh)),
                    "msfv_batch_get_options")
-        return s.value, bool(g.value)
+        return s.value, bool(g.value), sh.value
 
     def autotune(self, ms, vs):
-        """Time each candidate (streams x graphs) once and keep the fastest."""
+        """Time each candidate (shared launches in 1, 2 or 4 pipelines, or
+        the per-problem path with or without graphs, times the stream count)
+        once and keep the fastest; returns (streams, graphs, shared)."""
         self._check_inputs(ms, vs)
-        s, g = ctypes.c_int(), ctypes.c_int()
+        s, g, sh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _lib.check(self.lib.msfv_batch_autotune(self._h, _ptr_array(ms), _ptr_array(vs), self._dp,
-                                                self._gp, ctypes.byref(s), ctypes.byref(g)),
+                                                self._gp, ctypes.byref(s), ctypes.byref(g), ctypes.byref(sh)),
                    "msfv_batch_autotune")
-        return s.value, bool(g.value)
+        return s.value, bool(g.value), sh.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

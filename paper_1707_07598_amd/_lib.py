@@ -103,10 +103,10 @@ SIGNATURES = {
     "msfv_batch_forward_jtv": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                     ctypes.POINTER(_P)]),
     "msfv_batch_sync": (_I, [_P]),
-    "msfv_batch_set_options": (_I, [_P, _I, _I]),
-    "msfv_batch_get_options": (_I, [_P, _IP, _IP]),
+    "msfv_batch_set_options": (_I, [_P, _I, _I, _I]),
+    "msfv_batch_get_options": (_I, [_P, _IP, _IP, _IP]),
     "msfv_batch_autotune": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                 ctypes.POINTER(_P), _IP, _IP]),
+                                 ctypes.POINTER(_P), _IP, _IP, _IP]),
     "msfv_server_create": (_I, [_I, ctypes.c_double, ctypes.POINTER(_P)]),
     "msfv_server_destroy": (None, [_P]),
     "msfv_server_add_job": (_I, [_P, _P, _I, _IP]),

@@ -149,6 +149,7 @@ struct msfv_problem {
   // dual blocks split for launching: the full blocks of full_u^3 own cells
   // (geometry fixed at compile time) first, then the others
   DevBuf<int> d_blist;
+  std::vector<int> h_blist;
   int full_u = 0, nfull = 0, nrest = 0;
   // sensitivity passes (allocated on first use)
   DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
@@ -424,11 +425,23 @@ hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned 
                                  p->d_status.ptr, work, s);
 }
 
+// Launch caps of the full dual blocks of u^3 own cells (whatever the
+// other blocks of the grid are).
+void full_caps(msfv::LocalParams& lp, int u) {
+  lp.nu_cap = u * u * u;
+  lp.sig_cap = (u + 2) * (u + 2) * (u + 2);
+  lp.lane_cap = u * u;
+  lp.col_cap = u;
+  lp.nc_cap = 8;
+  lp.plane_cap = msfv::wave_plane(u, u) * u;
+}
+
 // Local solves of the dual blocks: the full blocks through the kernels
 // specialised for their shape, the others through the general ones.
 hipError_t launch_blocks(msfv_problem* p, const msfv::LocalParams& lp, bool adj, hipStream_t s) {
   if (p->nfull > 0) {
     msfv::LocalParams f = lp;
+    full_caps(f, p->full_u);
     f.ent_list = p->d_blist.ptr;
     f.nent = p->nfull;
     const hipError_t e = msfv::launch_wave_full(f, p->full_u, adj, s);
@@ -450,57 +463,96 @@ msfv_status ensure_ready(msfv_problem* p) {
   return MSFV_OK;
 }
 
-msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double* u_out) {
+// Parameters of the local stages.  kind 1 edges, 2 faces (or the dual
+// blocks of a 2-D grid), 3 dual blocks; adj selects the adjoint variant.
+msfv::LocalParams local_params(msfv_problem* p, int kind, bool adj) {
+  const msfv::Plan& P = p->plan;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
+  msfv::LocalParams lp = base_params(p);
+  lp.lagrange = lagrange ? 1 : 0;
+  if (kind == 1) {
+    lp.ents = p->d_edges.ptr;
+    lp.nent = int(P.edges.size());
+    return lp;
+  }
+  if (kind == 2) {
+    lp.ents = p->d_faces.ptr;
+    lp.nent = int(P.faces.size());
+    set_caps(lp, P.caps_face, P.max_nu_face);
+    if (adj) {
+      lp.mu_scratch = p->d_mu.ptr;
+      lp.recv = p->d_edges.ptr;
+      lp.push = lagrange ? 0 : 1;
+      lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
+      set_stats(p, lp, 3);
+    } else {
+      lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
+      set_stats(p, lp, 2);
+    }
+    return lp;
+  }
+  lp.ents = p->d_blocks.ptr;
+  lp.nent = int(P.blocks.size());
+  set_caps(lp, P.caps_block, P.max_nu_block);
+  if (adj) {
+    lp.mu_scratch = p->d_mu.ptr;
+    lp.recv = p->d_faces.ptr;
+    lp.push = lagrange ? 0 : 1;
+    lp.solve_adj = 1;
+    set_stats(p, lp, 1);
+  } else {
+    set_stats(p, lp, 0);
+  }
+  return lp;
+}
+
+// Forward, in three parts: the model of the call, the local solves (or the
+// frozen basis's energy blocks), and the Galerkin coarse problem with the
+// data.  A batch runs the middle part of many problems in shared launches.
+msfv_status fwd_begin(msfv_problem* p, const double* m) {
   msfv_status st = ensure_ready(p);
   if (st != MSFV_OK) return st;
   const msfv::Plan& P = p->plan;
   hipStream_t s = p->stream;
-  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
   HIP_OK(msfv::launch_zero(p->d_ent_it.ptr, p->d_ent_it.bytes(), s));
   STAGE(MSFV_STAGE_COPY_M,
         msfv::launch_prep_model(p->d_m.ptr, p->d_sig.ptr, m, P.ncell, p->d_status.ptr, s));
+  return MSFV_OK;
+}
 
-  msfv::LocalParams lp = base_params(p);
+msfv_status fwd_local(msfv_problem* p) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   if (p->frozen) {
     // fixed basis (eq. optredfixed): S_k stays, A_k(m) = S_k^T A(m) S_k from
     // energy blocks over each entity's fluxes at the current m
-    lp.ents = p->d_edges.ptr;
-    lp.nent = int(P.edges.size());
+    msfv::LocalParams lp = local_params(p, 1, false);
     lp.nc_cap = 2;
     STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_energy_frozen(lp, s));
-    lp.ents = p->d_faces.ptr;
-    lp.nent = int(P.faces.size());
-    lp.nc_cap = P.caps_face.nc;
+    lp = local_params(p, 2, false);
     STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_energy_frozen(lp, s));
     if (P.dim == 3) {
-      lp.ents = p->d_blocks.ptr;
-      lp.nent = int(P.blocks.size());
-      lp.nc_cap = P.caps_block.nc;
+      lp = local_params(p, 3, false);
       STAGE(MSFV_STAGE_BLOCK_FWD, msfv::launch_energy_frozen(lp, s));
     }
-  } else {
-  lp.ents = p->d_edges.ptr;
-  lp.nent = int(P.edges.size());
+    return MSFV_OK;
+  }
+  msfv::LocalParams lp = local_params(p, 1, false);
   STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
-
-  lp = base_params(p);
-  lp.ents = p->d_faces.ptr;
-  lp.nent = int(P.faces.size());
-  set_caps(lp, P.caps_face, P.max_nu_face);
-  lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
-  set_stats(p, lp, 2);
+  lp = local_params(p, 2, false);
   STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_local_fwd(lp, 0, s));
-
   if (P.dim == 3) {
-    lp = base_params(p);
-    lp.ents = p->d_blocks.ptr;
-    lp.nent = int(P.blocks.size());
-    set_caps(lp, P.caps_block, P.max_nu_block);
-    set_stats(p, lp, 0);
+    lp = local_params(p, 3, false);
     STAGE(MSFV_STAGE_BLOCK_FWD, launch_blocks(p, lp, false, s));
   }
-  }
+  return MSFV_OK;
+}
+
+msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
   STAGE(MSFV_STAGE_KASSEMBLE,
         msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_kent.ptr,
                                p->d_kval.ptr, p->d_kdia.ptr, int(P.kcol.size()), s));
@@ -529,11 +581,19 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
   return MSFV_OK;
 }
 
-msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
+msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double* u_out) {
+  msfv_status st = fwd_begin(p, m);
+  if (st == MSFV_OK) st = fwd_local(p);
+  if (st == MSFV_OK) st = fwd_end(p, d_out, u_out);
+  return st;
+}
+
+// J^T v in three parts: the adjoint coarse problem and the direct electrode
+// loads, the local adjoint sweeps (blocks, faces, edges), and g.
+msfv_status adj_begin(msfv_problem* p, const double* v) {
   if (!p->have_forward) return fail(MSFV_ESTATE, "msfv_jtv called before msfv_forward");
   const msfv::Plan& P = p->plan;
   hipStream_t s = p->stream;
-  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
   HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
@@ -547,36 +607,36 @@ msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
         msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
                            p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
                            p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
+  return MSFV_OK;
+}
+
+msfv_status adj_local(msfv_problem* p) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const bool lagrange = p->cfg.bc_mode == MSFV_BC_LAGRANGE;
   msfv::LocalParams lp;
   if (P.dim == 3) {
-    lp = base_params(p);
-    lp.ents = p->d_blocks.ptr;
-    lp.nent = int(P.blocks.size());
-    set_caps(lp, P.caps_block, P.max_nu_block);
-    lp.mu_scratch = p->d_mu.ptr;
-    lp.recv = p->d_faces.ptr;
-    lp.push = lagrange ? 0 : 1;
-    lp.solve_adj = 1;
-    set_stats(p, lp, 1);
+    lp = local_params(p, 3, true);
     STAGE(MSFV_STAGE_BLOCK_ADJ, launch_blocks(p, lp, true, s));
   }
-  lp = base_params(p);
-  lp.ents = p->d_faces.ptr;
-  lp.nent = int(P.faces.size());
-  set_caps(lp, P.caps_face, P.max_nu_face);
-  lp.mu_scratch = p->d_mu.ptr;
-  lp.recv = p->d_edges.ptr;
-  lp.push = lagrange ? 0 : 1;
-  lp.solve_adj = (lagrange && P.dim == 3) ? 0 : 1;
-  set_stats(p, lp, 3);
+  lp = local_params(p, 2, true);
   STAGE(MSFV_STAGE_FACE_ADJ, msfv::launch_local_adj(lp, 0, s));
-
-  lp = base_params(p);
-  lp.ents = p->d_edges.ptr;
-  lp.nent = int(P.edges.size());
+  lp = local_params(p, 1, true);
   STAGE(MSFV_STAGE_EDGE_ADJ, msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
-  STAGE(MSFV_STAGE_GFINAL, msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
   return MSFV_OK;
+}
+
+msfv_status adj_end(msfv_problem* p, double* g_out) {
+  hipStream_t s = p->stream;
+  STAGE(MSFV_STAGE_GFINAL, msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, p->plan.ncell, g_out, s));
+  return MSFV_OK;
+}
+
+msfv_status jtv_impl(msfv_problem* p, const double* v, double* g_out) {
+  msfv_status st = adj_begin(p, v);
+  if (st == MSFV_OK) st = adj_local(p);
+  if (st == MSFV_OK) st = adj_end(p, g_out);
+  return st;
 }
 
 
@@ -648,19 +708,13 @@ msfv_status jvp_impl(msfv_problem* p, const double* dm, double* dd_out) {
   lp.nent = int(P.faces.size());
   set_caps(lp, P.caps_face, P.max_nu_face);
   lp.prescribe = (lagrange && P.dim == 3) ? 1 : 0;
-  hipError_t e = msfv::launch_wave_tan(lp, s);
-  if (e == hipErrorInvalidConfiguration)
-    return fail(MSFV_EINVAL, "J dm needs entities that fit one wavefront (coarsening up to 8)");
-  HIP_OK(e);
+  HIP_OK(msfv::launch_local_tan(lp, s));
   if (P.dim == 3) {
     lp.ents = p->d_blocks.ptr;
     lp.nent = int(P.blocks.size());
     set_caps(lp, P.caps_block, P.max_nu_block);
     lp.prescribe = 0;
-    e = msfv::launch_wave_tan(lp, s);
-    if (e == hipErrorInvalidConfiguration)
-      return fail(MSFV_EINVAL, "J dm needs entities that fit one wavefront (coarsening up to 8)");
-    HIP_OK(e);
+    HIP_OK(msfv::launch_local_tan(lp, s));
   }
   HIP_OK(msfv::launch_kassemble(p->d_kcptr.ptr, p->d_kcidx.ptr, p->d_kdslot.ptr, p->d_dkent.ptr,
                                 p->d_dkval.ptr, p->d_dkdia.ptr, int(P.kcol.size()), s));
@@ -861,15 +915,6 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
   HIP_OR_CLEAN(p->d_inbuf.alloc(std::max<int64_t>(1, P.inbuf_size)));
   HIP_OR_CLEAN(p->d_W.alloc(size_t(3) * P.ncell));
   {
-    // scratch of the wave-level adjoint kernels (entities whose lane plane
-    // and column fit one wavefront)
-    auto fits = [](const msfv::Plan::Caps& c) { return c.lane <= 64 && c.col <= 7 && c.nc <= 8; };
-    size_t mu = 0;
-    if (fits(P.caps_block)) mu = std::max(mu, P.blocks.size() * 8 * size_t(std::max(1, P.max_nu_block)));
-    if (fits(P.caps_face)) mu = std::max(mu, P.faces.size() * 8 * size_t(std::max(1, P.max_nu_face)));
-    HIP_OR_CLEAN(p->d_mu.alloc(std::max<size_t>(1, mu)));
-  }
-  {
     // full dual blocks: U^3 own cells, bounded by vertex planes on every axis
     auto full_of = [](const msfv::EntDesc& E) {
       const int U = E.uext[0];
@@ -893,8 +938,20 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     p->nfull = int(full.size());
     p->nrest = int(rest.size());
     full.insert(full.end(), rest.begin(), rest.end());
+    p->h_blist = full;
     if (full.empty()) full.push_back(0);
     HIP_OR_CLEAN(p->d_blist.upload(full, s));
+  }
+  {
+    // scratch of the wave-level adjoint kernels (entities whose lane plane
+    // and column fit one wavefront, and the full dual blocks, which always
+    // take them): per entity 8 corners x the launch's own-cell cap
+    auto fits = [](const msfv::Plan::Caps& c) { return c.lane <= 64 && c.col <= 7 && c.nc <= 8; };
+    size_t mu = 0;
+    if (fits(P.caps_block)) mu = std::max(mu, P.blocks.size() * 8 * size_t(std::max(1, P.max_nu_block)));
+    if (p->nfull > 0) mu = std::max(mu, P.blocks.size() * 8 * size_t(p->full_u * p->full_u * p->full_u));
+    if (fits(P.caps_face)) mu = std::max(mu, P.faces.size() * 8 * size_t(std::max(1, P.max_nu_face)));
+    HIP_OR_CLEAN(p->d_mu.alloc(std::max<size_t>(1, mu)));
   }
   HIP_OR_CLEAN(p->d_m.alloc(P.ncell));
   HIP_OR_CLEAN(p->d_sig.alloc(P.ncell));
@@ -1194,6 +1251,37 @@ struct msfv_batch {
     hipGraphExec_t exec = nullptr;
   };
   std::vector<Graph> cache;      // one per problem
+  // shared mode: the local solves of the problems run as shared launches,
+  // one per kernel class and stage, over (problem, entity) items.  The
+  // problems are split into `shared` pipelines, each issued by a host thread
+  // of its own on its own streams, so one pipeline's local launches overlap
+  // another's coarse solves.
+  int shared = 0;
+  struct Group {
+    int stage = 0;   // 1 edges, 2 faces (2-D blocks), 3 dual blocks
+    bool adj = false;
+    int klass = 0;   // kernel class of the local solves (edges: 0)
+    msfv::LocalParams caps;  // largest caps of the class, for the launch
+    std::vector<int2> items;
+    DevBuf<int2> d_items;
+  };
+  struct Pipeline {
+    std::vector<int> members;                  // problem indices, largest first
+    std::vector<std::unique_ptr<Group>> groups;
+    DevBuf<msfv::LocalParams> d_params;
+    std::vector<unsigned long long> gen;       // member generations the groups were built for
+    hipStream_t main = nullptr;                // shared launches
+    std::vector<hipStream_t> streams;          // per-problem parts
+    hipEvent_t fork = nullptr, fin = nullptr;
+    std::vector<hipEvent_t> done;
+    ~Pipeline() {
+      if (fork) (void)hipEventDestroy(fork);
+      if (fin) (void)hipEventDestroy(fin);
+      for (auto e : done) (void)hipEventDestroy(e);
+    }
+  };
+  std::vector<std::unique_ptr<Pipeline>> pipes;
+  int pipes_streams = 0;  // stream count the pipelines were laid out for
   ~msfv_batch() {
     if (main) (void)hipStreamSynchronize(main);
     for (auto s : pool) (void)hipStreamSynchronize(s);
@@ -1253,14 +1341,240 @@ msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, do
   return st;
 }
 
+// The shared launches of a pipeline: per member problem, stage and kernel
+// class one parameter block; items grouped by (stage, direction, class).
+msfv_status shared_build(msfv_batch* b, msfv_batch::Pipeline* pl) {
+  std::vector<msfv::LocalParams> params;
+  std::map<std::tuple<int, int, int>, msfv_batch::Group*> index;
+  pl->groups.clear();
+  auto group = [&](int stage, bool adj, int klass) {
+    auto key = std::make_tuple(stage, adj ? 1 : 0, klass);
+    auto it = index.find(key);
+    if (it != index.end()) return it->second;
+    pl->groups.emplace_back(new msfv_batch::Group());
+    msfv_batch::Group* g = pl->groups.back().get();
+    g->stage = stage;
+    g->adj = adj;
+    g->klass = klass;
+    index[key] = g;
+    return g;
+  };
+  auto add = [&](msfv::LocalParams lp, int stage, bool adj, int klass, const int* ids, int count) {
+    if (count <= 0) return MSFV_OK;
+    if (stage > 1 && klass == msfv::kClassNone) return fail(MSFV_EINVAL, "an entity does not fit any local kernel");
+    lp.ent_work = nullptr;
+    lp.ent_list = nullptr;
+    if (stage > 1) lp.uni_cap = msfv::local_class_uni_cap(lp, klass);
+    const int pid = int(params.size());
+    params.push_back(lp);
+    msfv_batch::Group* g = group(stage, adj, klass);
+    msfv::LocalParams& c = g->caps;
+    c.nu_cap = std::max(c.nu_cap, lp.nu_cap);
+    c.sig_cap = std::max(c.sig_cap, lp.sig_cap);
+    c.lane_cap = std::max(c.lane_cap, lp.lane_cap);
+    c.col_cap = std::max(c.col_cap, lp.col_cap);
+    c.nc_cap = std::max(c.nc_cap, lp.nc_cap);
+    c.plane_cap = std::max(c.plane_cap, lp.plane_cap);
+    for (int k = 0; k < count; ++k) g->items.push_back(make_int2(pid, ids ? ids[k] : k));
+    return MSFV_OK;
+  };
+  for (int i : pl->members) {
+    msfv_problem* p = b->probs[i];
+    const msfv::Plan& P = p->plan;
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool adj = dir == 1;
+      msfv_status st = add(local_params(p, 1, adj), 1, adj, 0, nullptr, int(P.edges.size()));
+      if (st != MSFV_OK) return st;
+      msfv::LocalParams lf = local_params(p, 2, adj);
+      st = add(lf, 2, adj, msfv::local_class(lf), nullptr, int(P.faces.size()));
+      if (st != MSFV_OK) return st;
+      if (P.dim == 3) {
+        msfv::LocalParams lb = local_params(p, 3, adj);
+        if (p->nfull > 0) {
+          msfv::LocalParams lfull = lb;
+          full_caps(lfull, p->full_u);
+          st = add(lfull, 3, adj, msfv::full_class(p->full_u), p->h_blist.data(), p->nfull);
+        }
+        if (st == MSFV_OK)
+          st = add(lb, 3, adj, msfv::local_class(lb), p->h_blist.data() + p->nfull, p->nrest);
+        if (st != MSFV_OK) return st;
+      }
+    }
+  }
+  hipStream_t s = pl->main;
+  HIP_OK(pl->d_params.upload(params, s));
+  for (auto& g : pl->groups) {
+    HIP_OK(g->d_items.upload(g->items, s));
+    g->caps.multi = pl->d_params.ptr;
+    g->caps.items = g->d_items.ptr;
+    g->caps.nent = int(g->items.size());
+  }
+  // launch order: forward edges, faces, blocks; adjoint blocks, faces, edges
+  std::stable_sort(pl->groups.begin(), pl->groups.end(), [](const auto& x, const auto& y) {
+    const int kx = x->adj ? 10 - x->stage : x->stage, ky = y->adj ? 10 - y->stage : y->stage;
+    return kx < ky;
+  });
+  pl->gen.clear();
+  for (int i : pl->members) pl->gen.push_back(b->probs[i]->generation);
+  return MSFV_OK;
+}
+
+// Issue fn(problem, index) for every member of a pipeline over its streams
+// (forked from and joined into its main stream), members on the host-polled
+// coarse solver from worker threads.
+extern "C++" template <typename Fn>
+msfv_status issue_each(msfv_batch* b, msfv_batch::Pipeline* pl, Fn fn) {
+  const int ns = int(pl->streams.size());
+  HIP_OK(hipEventRecord(pl->fork, pl->main));
+  for (int k = 0; k < ns; ++k) HIP_OK(hipStreamWaitEvent(pl->streams[k], pl->fork, 0));
+  std::vector<int> polled, plain;
+  for (int i : pl->members) (ns > 1 && coarse_multi(b->probs[i]) ? polled : plain).push_back(i);
+  const int nw = polled.empty() ? 0 : std::min<int>(int(polled.size()), std::max(1, ns / 2));
+  std::vector<msfv_status> wst(nw, MSFV_OK);
+  std::vector<std::string> werr(nw);
+  std::vector<std::thread> workers;
+  int device = 0;
+  if (nw > 0) HIP_OK(hipGetDevice(&device));
+  auto one = [&](int i, hipStream_t s) {
+    msfv_problem* p = b->probs[i];
+    const hipStream_t own = p->stream;
+    const bool prof = p->prof.on;
+    p->stream = s;
+    p->prof.on = false;
+    const msfv_status st = fn(p, i);
+    p->stream = own;
+    p->prof.on = prof;
+    return st;
+  };
+  for (int w = 0; w < nw; ++w)
+    workers.emplace_back([&, w]() {
+      (void)hipSetDevice(device);
+      for (size_t k = w; k < polled.size(); k += nw) {
+        const msfv_status st = one(polled[k], pl->streams[w]);
+        if (st != MSFV_OK) {
+          wst[w] = st;
+          werr[w] = msfv_last_error();
+          return;
+        }
+      }
+    });
+  msfv_status st = MSFV_OK;
+  const int nplain = ns - nw;
+  for (size_t k = 0; k < plain.size() && st == MSFV_OK; ++k)
+    st = one(plain[k], nplain > 0 ? pl->streams[nw + int(k % nplain)] : pl->main);
+  for (auto& t : workers) t.join();
+  if (st != MSFV_OK) return st;
+  for (int w = 0; w < nw; ++w)
+    if (wst[w] != MSFV_OK) return fail(wst[w], werr[w]);
+  for (int k = 0; k < ns; ++k) {
+    HIP_OK(hipEventRecord(pl->done[k], pl->streams[k]));
+    HIP_OK(hipStreamWaitEvent(pl->main, pl->done[k], 0));
+  }
+  return MSFV_OK;
+}
+
+// One pipeline: per-problem parts on its streams, the local solves of its
+// members in shared launches on its main stream.
+msfv_status pipeline_run(msfv_batch* b, msfv_batch::Pipeline* pl, const double* const* m,
+                         const double* const* v, double* const* d_out, double* const* g_out) {
+  bool rebuild = pl->groups.empty() || pl->gen.size() != pl->members.size();
+  for (size_t k = 0; !rebuild && k < pl->members.size(); ++k)
+    rebuild = pl->gen[k] != b->probs[pl->members[k]]->generation;
+  if (rebuild) {
+    msfv_status st = shared_build(b, pl);
+    if (st != MSFV_OK) return st;
+  }
+  msfv_status st = issue_each(b, pl, [&](msfv_problem* p, int i) { return fwd_begin(p, m[i]); });
+  if (st != MSFV_OK) return st;
+  for (auto& g : pl->groups)
+    if (!g->adj)
+      HIP_OK(g->stage == 1 ? msfv::launch_edge_multi(g->caps, false, pl->main)
+                           : msfv::launch_local_multi(g->caps, g->klass, false, pl->main));
+  st = issue_each(b, pl, [&](msfv_problem* p, int i) {
+    msfv_status r = fwd_end(p, d_out[i], nullptr);
+    return r == MSFV_OK ? adj_begin(p, v[i]) : r;
+  });
+  if (st != MSFV_OK) return st;
+  for (auto& g : pl->groups)
+    if (g->adj)
+      HIP_OK(g->stage == 1 ? msfv::launch_edge_multi(g->caps, true, pl->main)
+                           : msfv::launch_local_multi(g->caps, g->klass, true, pl->main));
+  return issue_each(b, pl, [&](msfv_problem* p, int i) { return adj_end(p, g_out[i]); });
+}
+
+// Lay the problems out over b->shared pipelines: members dealt round-robin
+// from the largest-first order; pipeline q gets pool stream q as its main
+// stream and the pool streams k >= pipes (k < streams) with k % pipes == q.
+msfv_status shared_layout(msfv_batch* b) {
+  const int np = std::max(1, std::min<int>(b->shared, int(b->probs.size())));
+  const int ns = std::max(b->streams, np);
+  if (int(b->pipes.size()) == np && b->pipes_streams == ns) return MSFV_OK;
+  b->pipes.clear();
+  for (int q = 0; q < np; ++q) {
+    std::unique_ptr<msfv_batch::Pipeline> pl(new msfv_batch::Pipeline());
+    for (int k = q; k < int(b->order.size()); k += np) pl->members.push_back(b->order[k]);
+    pl->main = b->pool[q];
+    for (int k = np; k < ns && k < int(b->pool.size()); ++k)
+      if (k % np == q) pl->streams.push_back(b->pool[k]);
+    HIP_OK(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&pl->fin, hipEventDisableTiming));
+    for (size_t k = 0; k < pl->streams.size(); ++k) {
+      hipEvent_t e = nullptr;
+      HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      pl->done.push_back(e);
+    }
+    b->pipes.push_back(std::move(pl));
+  }
+  b->pipes_streams = ns;
+  return MSFV_OK;
+}
+
+// Shared mode: the pipelines run concurrently, each issued by a host thread.
+msfv_status shared_run(msfv_batch* b, const double* const* m, const double* const* v,
+                       double* const* d_out, double* const* g_out) {
+  msfv_status st = shared_layout(b);
+  if (st != MSFV_OK) return st;
+  HIP_OK(hipEventRecord(b->fork, b->main));
+  for (auto& pl : b->pipes) HIP_OK(hipStreamWaitEvent(pl->main, b->fork, 0));
+  const int np = int(b->pipes.size());
+  std::vector<msfv_status> pst(np, MSFV_OK);
+  std::vector<std::string> perr(np);
+  if (np == 1) {
+    pst[0] = pipeline_run(b, b->pipes[0].get(), m, v, d_out, g_out);
+    if (pst[0] != MSFV_OK) perr[0] = msfv_last_error();
+  } else {
+    int device = 0;
+    HIP_OK(hipGetDevice(&device));
+    std::vector<std::thread> th;
+    for (int q = 0; q < np; ++q)
+      th.emplace_back([&, q]() {
+        (void)hipSetDevice(device);
+        pst[q] = pipeline_run(b, b->pipes[q].get(), m, v, d_out, g_out);
+        if (pst[q] != MSFV_OK) perr[q] = msfv_last_error();
+      });
+    for (auto& t : th) t.join();
+  }
+  for (int q = 0; q < np; ++q)
+    if (pst[q] != MSFV_OK) return fail(pst[q], perr[q]);
+  for (auto& pl : b->pipes) {
+    HIP_OK(hipEventRecord(pl->fin, pl->main));
+    HIP_OK(hipStreamWaitEvent(b->main, pl->fin, 0));
+  }
+  return MSFV_OK;
+}
+
 msfv_status batch_run(msfv_batch* b, const double* const* m, const double* const* v,
                       double* const* d_out, double* const* g_out) {
   const int n = int(b->probs.size());
+  bool any_frozen = false;
   for (int i = 0; i < n; ++i) {
     if (!m[i] || !v[i] || !d_out[i] || !g_out[i]) return fail(MSFV_EINVAL, "null buffer in batch");
     msfv_status st = ensure_ready(b->probs[i]);
     if (st != MSFV_OK) return st;
+    any_frozen |= b->probs[i]->frozen;
   }
+  // frozen bases keep their own path (no local solves to share)
+  if (b->shared > 0 && !any_frozen) return shared_run(b, m, v, d_out, g_out);
   const int ns = std::min<int>(b->streams, int(b->pool.size()));
   HIP_OK(hipEventRecord(b->fork, b->main));
   for (int k = 0; k < ns; ++k) HIP_OK(hipStreamWaitEvent(b->pool[k], b->fork, 0));
@@ -1367,35 +1681,48 @@ msfv_status msfv_batch_sync(msfv_batch* b) {
   return MSFV_OK;
 }
 
-msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs) {
+msfv_status msfv_batch_set_options(msfv_batch* b, int streams, int graphs, int shared) {
   if (!b) return fail(MSFV_EINVAL, "null batch");
   if (streams < 1 || streams > int(b->pool.size())) return fail(MSFV_EINVAL, "streams outside [1, 16]");
+  if (shared < 0 || shared > 8) return fail(MSFV_EINVAL, "shared (pipelines) outside [0, 8]");
+  HIP_OK(hipStreamSynchronize(b->main));
+  for (auto s : b->pool) HIP_OK(hipStreamSynchronize(s));
   b->streams = streams;
   b->graphs = graphs != 0;
+  b->shared = shared;
   return MSFV_OK;
 }
 
-msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs) {
+msfv_status msfv_batch_get_options(msfv_batch* b, int* streams, int* graphs, int* shared) {
   if (!b) return fail(MSFV_EINVAL, "null batch");
   if (streams) *streams = b->streams;
   if (graphs) *graphs = b->graphs ? 1 : 0;
+  if (shared) *shared = b->shared;
   return MSFV_OK;
 }
 
 msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const double* const* v,
                                 double* const* d_out, double* const* g_out, int* streams_out,
-                                int* graphs_out) {
+                                int* graphs_out, int* shared_out) {
   if (!b || !m || !v || !d_out || !g_out) return fail(MSFV_EINVAL, "null argument");
   const int count = int(b->probs.size());
   double best = 1e300;
-  int best_s = b->streams;
+  int best_s = b->streams, best_sh = b->shared;
   bool best_g = b->graphs;
-  for (int gr = 1; gr >= 0; --gr) {
+  // candidates: shared launches of the local solves in 1, 2 or 4
+  // pipelines, or each problem's whole sequence on the stream pool, replayed
+  // from HIP graphs or issued eagerly; each over 1..16 streams
+  struct Cand {
+    int shared;
+    bool graphs;
+  };
+  for (const Cand c : {Cand{1, false}, Cand{2, false}, Cand{4, false}, Cand{0, true}, Cand{0, false}}) {
+    if (c.shared > count) continue;
     for (int sc : {1, 2, 4, 8, 16}) {
       if (sc > count && sc != 1) continue;
-      b->streams = sc;
-      b->graphs = gr != 0;
-      msfv_status st = batch_run(b, m, v, d_out, g_out);  // warm: captures graphs
+      if (c.shared > 1 && sc < 2 * c.shared) continue;  // a pipeline needs a stream besides its main one
+      (void)msfv_batch_set_options(b, sc, c.graphs ? 1 : 0, c.shared);
+      msfv_status st = batch_run(b, m, v, d_out, g_out);  // warm: captures graphs, builds shared launches
       if (st == MSFV_OK) st = msfv_batch_sync(b);
       if (st != MSFV_OK) return st;
       const auto t0 = std::chrono::steady_clock::now();
@@ -1406,14 +1733,16 @@ msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const dou
       if (dt < best) {
         best = dt;
         best_s = sc;
-        best_g = gr != 0;
+        best_g = c.graphs;
+        best_sh = c.shared;
       }
     }
   }
-  b->streams = best_s;
-  b->graphs = best_g;
+  msfv_status st = msfv_batch_set_options(b, best_s, best_g ? 1 : 0, best_sh);
+  if (st != MSFV_OK) return st;
   if (streams_out) *streams_out = best_s;
   if (graphs_out) *graphs_out = best_g ? 1 : 0;
+  if (shared_out) *shared_out = best_sh;
   return MSFV_OK;
 }
 

@@ -428,10 +428,8 @@ __device__ void load_closure_sigma(const EntDesc& E, const GridInfo& g, const do
 // forward: faces and dual blocks
 // ---------------------------------------------------------------------------
 template <int BLOCK, int CPT, int NCP>
-__global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, double* lds) {
   constexpr int NW = BLOCK / kWave;
-  const int eid = ent_index(a);
   const EntDesc& E = a.ents[eid];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
@@ -583,14 +581,185 @@ __global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
   }
 }
 
+template <int BLOCK, int CPT, int NCP, bool MULTI = false>
+__global__ __launch_bounds__(BLOCK) void k_local_fwd(LocalParams a) {
+  extern __shared__ double lds[];
+  if constexpr (MULTI) {
+    for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
+      const int2 w = a.items[it];
+      local_fwd_body<BLOCK, CPT, NCP>(a.multi[w.x], w.y, lds);
+      __syncthreads();  // the next item reuses the LDS tables
+    }
+  } else {
+    local_fwd_body<BLOCK, CPT, NCP>(a, ent_index(a), lds);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tangent (forward-mode J dm): faces and dual blocks that do not fit one
+// wavefront.  For each corner c, A^E_UU dphi_c = -(dA^E phi_c)_U -
+// A^E_UB dphi_c|_B (Sec. 4.5 differentiated along dm): the load is
+// -sum over the entity's fluxes at an own cell of dT_f (phi_c(i) - phi_c(n))
+// plus, towards Dirichlet neighbours, T_f dphi_c(n) from the lower entities'
+// tangents already in dS.  Then the tangent energy block dK_E = sum over the
+// touched fluxes of dT dphi dphi^T + T (d(dphi) dphi^T + dphi d(dphi)^T).
+// Prescribed (Lagrange) entities have dphi = 0 and only the dT term.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT, int NCP>
+__device__ __forceinline__ void local_tan_body(const LocalParams& a, int eid, double* lds) {
+  constexpr int NW = BLOCK / kWave;
+  const EntDesc& E = a.ents[eid];
+  double* sig = lds;
+  double* pb = sig + a.sig_cap;
+  double* redA = pb + NCP * a.nu_cap;
+  double* redB = redA + NW * 40;
+  double* tp = redB + NW * 40;  // 3 * nu_cap
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  __syncthreads();
+  CellGeo cg[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int u = threadIdx.x + j * BLOCK;
+    if (u < E.nu)
+      cell_setup(E, a.g, sig, u, cg[j], tp);
+    else
+      cg[j].u = -1;
+  }
+  __syncthreads();  // every cell's +k transmissibility is in tp
+  // dT of the flux of cell j in direction d (dm of the cell and of its neighbour)
+  auto dTf = [&](const CellGeo& c, int d) {
+    const int k = d >> 1;
+    const int ng = c.gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+    const int cn = c.ci + ((d & 1) ? cstride_of(E, k) : -cstride_of(E, k));
+    const double si = sig[c.ci], sn = sig[cn];
+    return dharm(si, sn) * a.dm[c.gid] + dharm(sn, si) * a.dm[ng];
+  };
+  const double tol2 = a.rtol * a.rtol;
+  bool all_ok = true;
+  for (int c0 = 0; c0 < E.nc; c0 += NCP) {
+    const int ncp = min(NCP, E.nc - c0);
+    double x[CPT][NCP];
+    if (a.prescribe) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) x[j][c] = 0.0;
+    } else {
+      double b[CPT][NCP];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) b[j][c] = 0.0;
+        if (cg[j].u < 0) continue;
+        const int base = a.prow[cg[j].gid] + c0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          if (!((cg[j].fmask >> d) & 1)) continue;
+          const bool own = (cg[j].umask >> d) & 1;
+          const int k = d >> 1;
+          const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+          const double dt = dTf(cg[j], d);
+          const double tt = cell_T(E, cg[j], d, sig, tp);
+#pragma unroll
+          for (int c = 0; c < NCP; ++c) {
+            if (c >= ncp) continue;
+            const int vid = E.vid[c0 + c];
+            const double pn = own ? a.pval[a.prow[ng] + c0 + c] : p_lookup(a.prow, a.pcol, a.pval, ng, vid);
+            b[j][c] -= dt * (a.pval[base + c] - pn);
+            if (!own) b[j][c] += tt * p_lookup(a.prow, a.pcol, a.dpval, ng, vid);
+          }
+        }
+      }
+      __syncthreads();  // previous pass finished with the LDS buffers
+      bool ok = true;
+      (void)local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      all_ok = all_ok && ok;
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (cg[j].u < 0) continue;
+      const int base = a.prow[cg[j].gid] + c0;
+#pragma unroll
+      for (int c = 0; c < NCP; ++c)
+        if (c < ncp) a.dpval[base + c] = x[j][c];
+    }
+  }
+  if (threadIdx.x == 0 && !all_ok) atomicAdd(a.status + kStLocalNoconv, 1);
+  __syncthreads();  // the tangent rows of this entity are visible to the workgroup
+
+  const int nc = E.nc;
+  double kacc[36];  // upper triangle (dK_E is symmetric)
+#pragma unroll
+  for (int i = 0; i < 36; ++i) kacc[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    if (cg[j].u < 0) continue;
+    double pu[8], du[8];
+    const int base = a.prow[cg[j].gid];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      pu[c] = c < nc ? a.pval[base + c] : 0.0;
+      du[c] = c < nc ? a.dpval[base + c] : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!((cg[j].fmask >> d) & 1)) continue;
+      const bool own = (cg[j].umask >> d) & 1;
+      if (!(d & 1) && own) continue;  // counted from the lower own cell
+      const int k = d >> 1;
+      const int ng = cg[j].gid + ((d & 1) ? gstride_of(a.g, k) : -gstride_of(a.g, k));
+      double dp[8], ddp[8];
+      const int nbase = a.prow[ng];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c >= nc) {
+          dp[c] = ddp[c] = 0.0;
+          continue;
+        }
+        const double pn = own ? a.pval[nbase + c] : p_lookup(a.prow, a.pcol, a.pval, ng, E.vid[c]);
+        const double dn = own ? a.dpval[nbase + c] : p_lookup(a.prow, a.pcol, a.dpval, ng, E.vid[c]);
+        dp[c] = pu[c] - pn;
+        ddp[c] = du[c] - dn;
+      }
+      const double tt = cell_T(E, cg[j], d, sig, tp);
+      const double dt = dTf(cg[j], d);
+      int q = 0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int c2 = c; c2 < 8; ++c2) {
+          kacc[q] += dt * dp[c] * dp[c2] + tt * (ddp[c] * dp[c2] + dp[c] * ddp[c2]);
+          ++q;
+        }
+    }
+  }
+  __syncthreads();
+  block_sum<NW, 36>(kacc, 36, redA);
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int c = 0; c < 8; ++c)
+      for (int c2 = c; c2 < 8; ++c2) {
+        if (c < nc && c2 < nc) {
+          a.kent[E.kbase + c * nc + c2] = kacc[q];
+          a.kent[E.kbase + c2 * nc + c] = kacc[q];
+        }
+        ++q;
+      }
+  }
+}
+
+template <int BLOCK, int CPT, int NCP>
+__global__ __launch_bounds__(BLOCK) void k_local_tan(LocalParams a) {
+  extern __shared__ double lds[];
+  local_tan_body<BLOCK, CPT, NCP>(a, ent_index(a), lds);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint: dual blocks and faces
 // ---------------------------------------------------------------------------
 template <int BLOCK, int CPT, int NCP>
-__global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void local_adj_body(const LocalParams& a, int eid, double* lds) {
   constexpr int NW = BLOCK / kWave;
-  const int eid = ent_index(a);
   const EntDesc& E = a.ents[eid];
   double* sig = lds;
   double* pb = sig + a.sig_cap;
@@ -830,6 +999,20 @@ __global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
   }
 }
 
+template <int BLOCK, int CPT, int NCP, bool MULTI = false>
+__global__ __launch_bounds__(BLOCK) void k_local_adj(LocalParams a) {
+  extern __shared__ double lds[];
+  if constexpr (MULTI) {
+    for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
+      const int2 w = a.items[it];
+      local_adj_body<BLOCK, CPT, NCP>(a.multi[w.x], w.y, lds);
+      __syncthreads();  // the next item reuses the LDS tables
+    }
+  } else {
+    local_adj_body<BLOCK, CPT, NCP>(a, ent_index(a), lds);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // edges: closed-form forward, tridiagonal adjoint (one thread per edge)
 // ---------------------------------------------------------------------------
@@ -869,9 +1052,7 @@ __device__ __forceinline__ void edge_phi(const EntDesc& E, const EdgeLine& L, co
   }
 }
 
-__global__ void k_edge_fwd(LocalParams a, int lagrange) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nent) return;
+__device__ __forceinline__ void edge_fwd_one(const LocalParams& a, int e, int lagrange) {
   const EntDesc E = a.ents[e];
   EdgeLine L;
   edge_line(E, a.g, a.m, L);
@@ -904,6 +1085,12 @@ __global__ void k_edge_fwd(LocalParams a, int lagrange) {
     a.kent[E.kbase + 2] = k01;
     a.kent[E.kbase + 3] = k11;
   }
+}
+
+__global__ void k_edge_fwd(LocalParams a, int lagrange) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nent) return;
+  edge_fwd_one(a, e, lagrange);
 }
 
 // Tangent of the edge basis along dm (Sec. 4.5, forward mode): with
@@ -967,9 +1154,7 @@ __global__ void k_edge_tan(LocalParams a, int lagrange) {
   a.kent[E.kbase + 3] = k11;
 }
 
-__global__ void k_edge_adj(LocalParams a, int lagrange) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nent) return;
+__device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int lagrange) {
   const EntDesc E = a.ents[e];
   EdgeLine L;
   edge_line(E, a.g, a.m, L);
@@ -1049,6 +1234,24 @@ __global__ void k_edge_adj(LocalParams a, int lagrange) {
     const double w = -((mu0[i] - mu0[i + 1]) * d0 + (mu1[i] - mu1[i + 1]) * d1) - quad;
     Wk[L.base + i * L.st] = w;
   }
+}
+
+__global__ void k_edge_adj(LocalParams a, int lagrange) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nent) return;
+  edge_adj_one(a, e, lagrange);
+}
+
+// edges of many problems: one thread an item
+__global__ void k_edge_multi(LocalParams a, int adj) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= a.nent) return;
+  const int2 w = a.items[it];
+  const LocalParams& A = a.multi[w.x];
+  if (adj)
+    edge_adj_one(A, w.y, A.lagrange);
+  else
+    edge_fwd_one(A, w.y, A.lagrange);
 }
 
 // ---------------------------------------------------------------------------
@@ -1338,40 +1541,119 @@ size_t local_lds_bytes(const LocalParams& p, bool adj) {
   return d * sizeof(double);
 }
 
-template <int BLOCK, int CPT, int NCP>
+template <int BLOCK, int CPT, int NCP, bool MULTI = false>
 hipError_t launch_local_t(const LocalParams& p, bool adj, hipStream_t s) {
   const size_t lds = local_lds_bytes<BLOCK, CPT, NCP>(p, adj);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  unsigned grid = unsigned(p.nent);
+  if constexpr (MULTI) {
+    // a fixed grid of as many workgroups as fit the device at once
+    const int per_cu = std::max(1, std::min<int>(int((160 * 1024) / std::max<size_t>(lds, 1)), 2048 / BLOCK));
+    grid = unsigned(std::min<long long>(p.nent, 256LL * per_cu));
+  }
   if (adj) {
-    auto kern = k_local_adj<BLOCK, CPT, NCP>;
+    auto kern = k_local_adj<BLOCK, CPT, NCP, MULTI>;
     if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(BLOCK), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, p);
   } else {
-    auto kern = k_local_fwd<BLOCK, CPT, NCP>;
+    auto kern = k_local_fwd<BLOCK, CPT, NCP, MULTI>;
     if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(BLOCK), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, p);
   }
   return hipGetLastError();
+}
+
+// The generic variants, by own-cell count (and corners): index i of
+// kClassLocalFirst + i.
+int generic_index(const LocalParams& p) {
+  const int nu = p.nu_cap;
+  if (nu <= 64) return 0;
+  if (nu <= 128) return 1;
+  if (nu <= 256) return p.nc_cap <= 4 ? 2 : 3;  // faces (4 corners): all corners in one pass
+  if (nu <= 384) return 4;
+  if (nu <= 512) return 5;
+  if (nu <= 1024) return 6;
+  // LDS: sigma, one direction, tp (four cells a thread at 1024 threads spilled
+  // more and ran 1.7x slower at r = 16)
+  if (nu <= 4096) return 7;
+  return -1;
+}
+
+template <bool MULTI>
+hipError_t launch_generic(int idx, const LocalParams& p, bool adj, hipStream_t s) {
+  switch (idx) {
+    case 0: return launch_local_t<64, 1, 8, MULTI>(p, adj, s);
+    case 1: return launch_local_t<128, 1, 8, MULTI>(p, adj, s);
+    case 2: return launch_local_t<256, 1, 4, MULTI>(p, adj, s);
+    case 3: return launch_local_t<256, 1, 8, MULTI>(p, adj, s);
+    case 4: return launch_local_t<384, 1, 8, MULTI>(p, adj, s);
+    case 5: return launch_local_t<512, 1, 8, MULTI>(p, adj, s);
+    case 6: return launch_local_t<1024, 1, 4, MULTI>(p, adj, s);
+    case 7: return launch_local_t<512, 8, 1, MULTI>(p, adj, s);
+    default: return hipErrorInvalidConfiguration;
+  }
 }
 
 hipError_t launch_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
   if (wave_path_fits(p)) return launch_wave_local(p, adj, s);
-  const int nu = p.nu_cap;
-  if (nu <= 64) return launch_local_t<64, 1, 8>(p, adj, s);
-  if (nu <= 128) return launch_local_t<128, 1, 8>(p, adj, s);
-  if (nu <= 256)  // faces (4 corners) solve all their corners in one pass of half the registers
-    return p.nc_cap <= 4 ? launch_local_t<256, 1, 4>(p, adj, s) : launch_local_t<256, 1, 8>(p, adj, s);
-  if (nu <= 384) return launch_local_t<384, 1, 8>(p, adj, s);
-  if (nu <= 512) return launch_local_t<512, 1, 8>(p, adj, s);
-  if (nu <= 1024) return launch_local_t<1024, 1, 4>(p, adj, s);
-  // LDS: sigma, one direction, tp (four cells a thread at 1024 threads spilled
-  // more and ran 1.7x slower at r = 16)
-  if (nu <= 4096) return launch_local_t<512, 8, 1>(p, adj, s);
-  return hipErrorInvalidConfiguration;
+  return launch_generic<false>(generic_index(p), p, adj, s);
 }
 
 }  // namespace
+
+template <int BLOCK, int CPT, int NCP>
+hipError_t launch_tan_generic_t(const LocalParams& p, hipStream_t s) {
+  const size_t lds = local_lds_bytes<BLOCK, CPT, NCP>(p, false);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  auto kern = k_local_tan<BLOCK, CPT, NCP>;
+  if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL(kern, dim3(p.nent), dim3(BLOCK), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_tan(const LocalParams& p, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!p.dm || !p.dpval) return hipErrorInvalidValue;
+  if (wave_path_fits(p)) return launch_wave_tan(p, s);
+  switch (generic_index(p)) {
+    case 0: return launch_tan_generic_t<64, 1, 8>(p, s);
+    case 1: return launch_tan_generic_t<128, 1, 8>(p, s);
+    case 2: return launch_tan_generic_t<256, 1, 4>(p, s);
+    case 3: return launch_tan_generic_t<256, 1, 8>(p, s);
+    case 4: return launch_tan_generic_t<384, 1, 8>(p, s);
+    case 5: return launch_tan_generic_t<512, 1, 8>(p, s);
+    case 6: return launch_tan_generic_t<1024, 1, 4>(p, s);
+    case 7: return launch_tan_generic_t<512, 8, 1>(p, s);
+    default: return hipErrorInvalidConfiguration;
+  }
+}
+
+int local_class(const LocalParams& p) {
+  if (wave_path_fits(p)) return wave_class(p);
+  const int idx = generic_index(p);
+  return idx < 0 ? kClassNone : kClassLocalFirst + idx;
+}
+
+int full_class(int u) { return u == 7 ? kClassFull7 : (u == 3 ? kClassFull3 : kClassNone); }
+
+int local_class_uni_cap(const LocalParams& p, int klass) {
+  return klass < kClassLocalFirst ? wave_class_uni_cap(p, klass) : 0;
+}
+
+hipError_t launch_local_multi(const LocalParams& p, int klass, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!p.multi || !p.items) return hipErrorInvalidValue;
+  if (klass >= kClassLocalFirst) return launch_generic<true>(klass - kClassLocalFirst, p, adj, s);
+  return launch_wave_multi(p, klass, adj, s);
+}
+
+hipError_t launch_edge_multi(const LocalParams& p, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!p.multi || !p.items) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_edge_multi, dim3((p.nent + 127) / 128), dim3(128), 0, s, p, adj ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_check_finite(const double* m, long long n, int* status, hipStream_t s) {
   const int threads = 256;

@@ -68,6 +68,12 @@ struct LocalParams {
   const double* dm = nullptr;             // tangent passes: direction of the model perturbation
   double* dpval = nullptr;                // tangent passes: dS_k values (CSR of S_k)
   const int* ent_list = nullptr;          // if set: workgroup b solves entity ent_list[b] of ents
+  int lagrange = 0;                       // edges of multi-instance launches: Lagrange boundary values
+  // Multi-instance launches (many problems, one launch): item i of the nent
+  // items is entity items[i].y of the problem whose parameters are
+  // multi[items[i].x]; a fixed grid of workgroups strides over the items.
+  const LocalParams* multi = nullptr;
+  const int2* items = nullptr;
 };
 
 // The entity of this workgroup (per-entity outputs are indexed by it).
@@ -134,6 +140,27 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
 // from the S_k values in p.pval and p.sig = exp(m), into p.kent: A_k of a
 // frozen basis (wave_kernels.hip)
 hipError_t launch_energy_frozen(const LocalParams& p, hipStream_t s);
+// Multi-instance local solves.  A class is the kernel variant that
+// launch_local_* (or launch_wave_full, for the full blocks) would pick for a
+// problem's entity list; items of one class from many problems run in one
+// launch of a fixed grid.  p carries multi, items, nent and the largest caps
+// over the problems of the class (for the LDS size).
+enum LocalClass {
+  kClassNone = 0,
+  kClassWave441 = 1, kClassWave443, kClassWave447, kClassWave481, kClassWave483, kClassWave487,
+  kClassFull3, kClassFull7,
+  kClassLocalFirst = 16  // + index of the generic variant
+};
+int local_class(const LocalParams& p);      // class of a problem's launch (caps of p)
+int full_class(int u);                      // class of full u^3 blocks
+// uni_cap a problem's parameters must carry in a launch of class klass
+int local_class_uni_cap(const LocalParams& p, int klass);
+hipError_t launch_local_multi(const LocalParams& p, int klass, bool adj, hipStream_t s);
+hipError_t launch_edge_multi(const LocalParams& p, bool adj, hipStream_t s);
+// wave-kernel classes (wave_kernels.hip)
+int wave_class(const LocalParams& p);
+int wave_class_uni_cap(const LocalParams& p, int klass);
+hipError_t launch_wave_multi(const LocalParams& p, int klass, bool adj, hipStream_t s);
 // wave-per-corner local solves (wave_kernels.hip)
 bool wave_path_fits(const LocalParams& p);
 hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);
@@ -169,6 +196,9 @@ hipError_t launch_prep_model(double* dst, double* sig, const double* src, long l
 hipError_t launch_edge_tan(const LocalParams& p, int lagrange, hipStream_t s);
 // tangent face / dual-block basis and energy blocks (wave_kernels.hip)
 hipError_t launch_wave_tan(const LocalParams& p, hipStream_t s);
+// the same for any entity size: the wave kernels where they fit, else the
+// workgroup-per-entity kernels (kernels.hip)
+hipError_t launch_local_tan(const LocalParams& p, hipStream_t s);
 // y_j = (dA/dm . dm) u_j for all ns columns of u (N each)
 hipError_t launch_dAu(const double* m, const double* dm, GridInfo g, long long ncell, int ns,
                       const double* u, double* y, hipStream_t s);

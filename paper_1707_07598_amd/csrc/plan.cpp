@@ -304,7 +304,7 @@ std::string Plan::build(int dim_, const int n_[3], const int r_[3]) {
       c->lane = std::max(c->lane, ua * ub);
       c->col = std::max(c->col, L);
       c->nc = std::max(c->nc, e.nc);
-      c->plane = std::max(c->plane, (ua + 2) * (ub + 2) * L);
+      c->plane = std::max(c->plane, wave_plane(ua, ub) * L);
       c->closure = std::max(c->closure, e.cext[0] * e.cext[1] * e.cext[2]);
     }
   };

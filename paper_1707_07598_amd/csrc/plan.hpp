@@ -19,6 +19,15 @@ namespace msfv {
 
 constexpr int kMaxCorners = 8;
 
+// Zero-padded plane buffer of the wave-per-corner local solves, for an own
+// box of ua x ub columns: rows of 8 doubles (lane (ia, ib) at row ib + 1,
+// entry ia + 1; entry 0 of each row is both its left pad and the previous
+// row's right pad) when ua <= 7 and ub <= 8, so each 16-lane quarter of a
+// wave reads 16 consecutive doubles; otherwise rows of ua + 2.  Doubles per
+// plane (the column axis multiplies it).
+constexpr int wave_plane_row(int ua, int ub) { return (ua <= 7 && ub <= 8) ? 8 : ua + 2; }
+constexpr int wave_plane(int ua, int ub) { return wave_plane_row(ua, ub) * (ub + 2); }
+
 // Entity descriptor shared by host and device (plain data, 4-byte fields).
 struct EntDesc {
   int clo[3];        // closure box: global lower corner

@@ -133,6 +133,7 @@ struct WGeo {
   int ua, ub, uc;  // own-index strides
   int ga, gb, gc;  // global strides
   int sa, sb, sc;  // closure strides
+  int lw;          // lanes a row of the lane plane (lane = ia + lw * ib)
   int pa, plane;   // padded row length and padded plane size
   int g0, s0;      // global id and closure index of the own-box origin
 };
@@ -163,8 +164,11 @@ __device__ __forceinline__ WGeo wave_geo(const EntDesc& E, const GridInfo& g) {
   w.sa = sel3(w.axa, 1, cs1, cs2);
   w.sb = sel3(w.axb, 1, cs1, cs2);
   w.sc = sel3(w.axc, 1, cs1, cs2);
-  w.pa = w.Ua + 2;
-  w.plane = (w.Ua + 2) * (w.Ub + 2);
+  // rows of 8 lanes and 8 doubles where the box allows: a 16-lane quarter
+  // of the wave then touches 16 consecutive doubles of the plane buffer
+  w.pa = wave_plane_row(w.Ua, w.Ub);
+  w.lw = w.pa == 8 ? 8 : w.Ua;
+  w.plane = wave_plane(w.Ua, w.Ub);
   w.g0 = E.ulo[0] + g.s1 * E.ulo[1] + g.s2 * E.ulo[2];
   w.s0 = (E.ulo[0] - E.clo[0]) + cs1 * (E.ulo[1] - E.clo[1]) + cs2 * (E.ulo[2] - E.clo[2]);
   return w;
@@ -759,8 +763,8 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
   shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
-  const bool valid = lane < w.Ua * w.Ub;
+  const int ia0 = lane % w.lw, ib0 = lane / w.lw;
+  const bool valid = ia0 < w.Ua && ib0 < w.Ub;
   Column<LMAX> C;
   if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead from here on; pbuf aliases it
@@ -1005,16 +1009,29 @@ __device__ __forceinline__ EntDesc full_block(const EntDesc& src) {
   return E;
 }
 
-// FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks.
-template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
-  extern __shared__ double lds[];
-  const int eid = ent_index(a);
+template <int NWAVE, int NCMAX, int LMAX, int FULLU>
+__device__ __forceinline__ void wave_fwd_one(const LocalParams& a, int eid, double* lds) {
   if constexpr (FULLU > 0) {
     const EntDesc E = full_block<FULLU>(a.ents[eid]);
     wave_fwd_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
   } else {
     wave_fwd_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
+  }
+}
+
+// FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks.
+// MULTI: a fixed grid strides over (problem, entity) items of many problems.
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
+  extern __shared__ double lds[];
+  if constexpr (MULTI) {
+    for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
+      const int2 w = a.items[it];
+      wave_fwd_one<NWAVE, NCMAX, LMAX, FULLU>(a.multi[w.x], w.y, lds);
+      __syncthreads();  // the next item reuses the LDS tables
+    }
+  } else {
+    wave_fwd_one<NWAVE, NCMAX, LMAX, FULLU>(a, ent_index(a), lds);
   }
 }
 
@@ -1086,8 +1103,8 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
     S.sbase[threadIdx.x] = base;
   }
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
-  const bool valid = lane < w.Ua * w.Ub;
+  const int ia0 = lane % w.lw, ib0 = lane / w.lw;
+  const bool valid = ia0 < w.Ua && ib0 < w.Ub;
   const bool any = wid < nc && loaded;
   __syncthreads();
   Column<LMAX> C;
@@ -1359,15 +1376,27 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
 }
 
 
-template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
-  extern __shared__ double lds[];
-  const int eid = ent_index(a);
+template <int NWAVE, int NCMAX, int LMAX, int FULLU>
+__device__ __forceinline__ void wave_adj_one(const LocalParams& a, int eid, double* lds) {
   if constexpr (FULLU > 0) {
     const EntDesc E = full_block<FULLU>(a.ents[eid]);
     wave_adj_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
   } else {
     wave_adj_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
+  }
+}
+
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
+  extern __shared__ double lds[];
+  if constexpr (MULTI) {
+    for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
+      const int2 w = a.items[it];
+      wave_adj_one<NWAVE, NCMAX, LMAX, FULLU>(a.multi[w.x], w.y, lds);
+      __syncthreads();
+    }
+  } else {
+    wave_adj_one<NWAVE, NCMAX, LMAX, FULLU>(a, ent_index(a), lds);
   }
 }
 
@@ -1401,8 +1430,8 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
   shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int ia0 = lane % w.Ua, ib0 = lane / w.Ua;
-  const bool valid = lane < w.Ua * w.Ub;
+  const int ia0 = lane % w.lw, ib0 = lane / w.lw;
+  const bool valid = ia0 < w.Ua && ib0 < w.Ub;
   Column<LMAX> C;
   if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead; pbuf aliases it
@@ -1542,25 +1571,39 @@ size_t wave_lds_bytes(const LocalParams& p) {
   return (size_t(1 + PHIC) * p.sig_cap + p.nu_cap + 128 + 40 + RED * 36 + size_t(p.uni_cap)) * sizeof(double);
 }
 
-template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0>
+// Shared plane-buffer region of the wave kernels: one plane buffer a wave,
+// or four (one a corner) for the one-wave path, and at least the 6 nu
+// scaled transmissibilities.
+template <int NWAVE>
+int wave_uni_cap(const LocalParams& p) {
+  const size_t bufs = NWAVE == 1 ? 4 : NWAVE;
+  return int(std::max(size_t(6) * p.nu_cap, bufs * p.plane_cap));
+}
+
+template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
 hipError_t launch_wave_t(const LocalParams& pin, bool adj, hipStream_t s) {
   LocalParams p = pin;
-  // plane buffers: one a wave, or four (one a corner) for the one-wave path
-  const size_t bufs = NWAVE == 1 ? 4 : NWAVE;
-  p.uni_cap = int(std::max(size_t(6) * p.nu_cap, bufs * p.plane_cap));
+  p.uni_cap = wave_uni_cap<NWAVE>(p);
   const size_t lds = wave_lds_bytes<NWAVE, NCMAX, NWAVE>(p);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  if (adj && !p.mu_scratch) return hipErrorInvalidValue;
+  if (adj && !MULTI && !p.mu_scratch) return hipErrorInvalidValue;
+  // MULTI: a fixed grid of as many workgroups as fit the device at once
+  // (compute units x workgroups a compute unit by LDS), striding over items
+  unsigned grid = unsigned(p.nent);
+  if constexpr (MULTI) {
+    const int per_cu = std::max(1, std::min<int>(int((160 * 1024) / std::max<size_t>(lds, 1)), 2048 / (NWAVE * 64)));
+    grid = unsigned(std::min<long long>(p.nent, 256LL * per_cu));
+  }
   if (adj) {
-    auto kern = k_wave_adj<NWAVE, NCMAX, LMAX, FULLU>;
+    auto kern = k_wave_adj<NWAVE, NCMAX, LMAX, FULLU, MULTI>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NWAVE * 64), lds, s, p);
   } else {
-    auto kern = k_wave_fwd<NWAVE, NCMAX, LMAX, FULLU>;
+    auto kern = k_wave_fwd<NWAVE, NCMAX, LMAX, FULLU, MULTI>;
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL(kern, dim3(p.nent), dim3(NWAVE * 64), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NWAVE * 64), lds, s, p);
   }
   return hipGetLastError();
 }
@@ -1598,6 +1641,36 @@ hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.col_cap <= 1) return launch_wave_t<4, 8, 1>(p, adj, s);
   if (p.col_cap <= 3) return launch_wave_t<4, 8, 3>(p, adj, s);
   return launch_wave_t<4, 8, 7>(p, adj, s);
+}
+
+// Class of the wave launch launch_wave_local would make for p's caps.
+int wave_class(const LocalParams& p) {
+  if (p.nc_cap <= 4) {
+    if (p.col_cap <= 1) return kClassWave441;
+    if (p.col_cap <= 3) return kClassWave443;
+    return kClassWave447;
+  }
+  if (p.col_cap <= 1) return kClassWave481;
+  if (p.col_cap <= 3) return kClassWave483;
+  return kClassWave487;
+}
+
+int wave_class_uni_cap(const LocalParams& p, int klass) {
+  return klass == kClassWave441 ? wave_uni_cap<1>(p) : wave_uni_cap<4>(p);
+}
+
+hipError_t launch_wave_multi(const LocalParams& p, int klass, bool adj, hipStream_t s) {
+  switch (klass) {
+    case kClassWave441: return launch_wave_t<1, 4, 1, 0, true>(p, adj, s);
+    case kClassWave443: return launch_wave_t<4, 4, 3, 0, true>(p, adj, s);
+    case kClassWave447: return launch_wave_t<4, 4, 7, 0, true>(p, adj, s);
+    case kClassWave481: return launch_wave_t<4, 8, 1, 0, true>(p, adj, s);
+    case kClassWave483: return launch_wave_t<4, 8, 3, 0, true>(p, adj, s);
+    case kClassWave487: return launch_wave_t<4, 8, 7, 0, true>(p, adj, s);
+    case kClassFull3: return launch_wave_t<4, 8, 3, 3, true>(p, adj, s);
+    case kClassFull7: return launch_wave_t<4, 8, 7, 7, true>(p, adj, s);
+    default: return hipErrorInvalidConfiguration;
+  }
 }
 
 hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s) {

@@ -20,7 +20,8 @@ SHAPES = [((13, 11, 9), (4, 4, 4), 3, "twolevel"),
           ((36, 20, 19), (16, 8, 6), 2, "twolevel"),    # r = 16 along x: the generic local kernels
           ((32, 32), (4, 4), 2, "multi"),               # 2-D
           ((17, 9, 12), (8, 3, 4), 5, "multi"),
-          ((24, 22, 20), (8, 8, 8), 1, "twolevel")]
+          ((24, 22, 20), (8, 8, 8), 1, "twolevel"),
+          ((33, 33, 17), (16, 16, 16), 2, "twolevel")]  # full 7^3 block among generic ones
 
 
 @pytest.fixture(scope="module")
@@ -90,16 +91,28 @@ def test_graph_replays_and_in_place_updates(batch_setup):
 
 
 def test_options_autotune_and_new_buffers(batch_setup):
+    """Stream counts, graphs on and off, and shared launches of the local
+    solves across problems (one launch per stage and kernel class over
+    (problem, entity) items) in 1 to 4 pipelines: every option gives the
+    eager results bit for bit; the autotuner's choice too."""
     import torch
     insts, probs, ms, vs, eager, b = batch_setup
-    for streams, graphs in [(1, False), (3, False), (16, True), (1, True)]:
-        b.set_options(streams, graphs)
-        assert b.options() == (streams, graphs)
-        D, g = b.forward_jtv(ms, vs)
-        for k in range(len(probs)):
-            assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), (streams, graphs, k)
-    s, gr = b.autotune(ms, vs)
+    for streams, graphs, shared in [(1, False, 0), (3, False, 0), (16, True, 0), (1, True, 0),
+                                    (1, False, 1), (4, False, 1), (16, False, 1), (1, False, 2),
+                                    (5, False, 2), (16, False, 4), (8, False, 8)]:
+        b.set_options(streams, graphs, shared)
+        assert b.options() == (streams, graphs, shared)
+        for rep in range(2):
+            D, g = b.forward_jtv(ms, vs)
+            for k in range(len(probs)):
+                assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), \
+                    (streams, graphs, shared, rep, k)
+    s, gr, sh = b.autotune(ms, vs)
     assert 1 <= s <= 16
+    assert b.options() == (s, gr, sh)
+    D, g = b.forward_jtv(ms, vs)
+    for k in range(len(probs)):
+        assert torch.equal(D[k], eager[k][0]) and torch.equal(g[k], eager[k][1]), k
     # new input buffers: graphs are captured again
     ms2 = [m.clone() for m in ms]
     D, g = b.forward_jtv(ms2, vs)
@@ -170,6 +183,7 @@ def test_batch_after_a_source_change():
         insts.append(inst)
         ms.append(torch.tensor(inst.m, dtype=torch.float64, device="cuda"))
     b = msfv.Batch(probs)
+    b.set_options(4, False, 2)  # shared launches in two pipelines: rebuilt after the change
     for ns_new in (None, 5, 1):
         if ns_new is not None:
             probs[1].set_sources(W.surface_dipoles(insts[1].n, ns_new))

@@ -25,6 +25,7 @@ CASES = [
     ((17, 9, 12), (8, 3, 4)),     # r = 8 with a 1-cell last coarse cell (empty upper strip)
     ((18, 10, 7), (5, 3, 3)),     # 2-cell last coarse cells
     ((40, 36, 34), (16, 16, 16)), # r = 16: a dual block of 15^3 own cells (generic kernels)
+    ((33, 33, 17), (16, 16, 16)), # r = 16 with one full 7^3 block among 15 x 15 x 7 ones (both paths)
     ((40, 36), (16, 16)),         # 2-D r = 16: 15^2 own cells, 4 corners (generic kernels)
     ((32, 32), (4, 4)),           # 2-D
     ((23, 17), (5, 6)),           # 2-D truncated
