@@ -150,6 +150,7 @@ struct msfv_problem {
   // (geometry fixed at compile time) first, then the others
   DevBuf<int> d_blist;
   std::vector<int> h_blist;
+  DevBuf<int> d_flist;  // faces in launch order
   int full_u = 0, nfull = 0, nrest = 0;
   // sensitivity passes (allocated on first use)
   DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
@@ -370,6 +371,23 @@ msfv_status build_electrodes(msfv_problem* p) {
   return MSFV_OK;
 }
 
+// Workgroups go round-robin over the eight XCDs (workgroup k to XCD k mod 8),
+// each with its own L2.  The launch order of a list of entities deals them so
+// that XCD x runs the x-th contiguous run of the list: neighbouring entities,
+// which read the same lower-dimensional rows and the same m on their shared
+// closure cells and write S_k rows into the same lines, meet in one L2.
+std::vector<int> deal_over_xcds(const std::vector<int>& list) {
+  const int nb = int(list.size()), q = nb / 8, r = nb % 8;
+  std::vector<int> dealt(list.size());
+  int start = 0;
+  for (int x = 0; x < 8; ++x) {
+    const int len = q + (x < r ? 1 : 0);
+    for (int j = 0; j < len; ++j) dealt[size_t(8) * j + x] = list[size_t(start) + j];
+    start += len;
+  }
+  return dealt;
+}
+
 msfv::LocalParams base_params(msfv_problem* p) {
   msfv::LocalParams lp;
   lp.g = p->g;
@@ -477,6 +495,7 @@ msfv::LocalParams local_params(msfv_problem* p, int kind, bool adj) {
   }
   if (kind == 2) {
     lp.ents = p->d_faces.ptr;
+    lp.ent_list = p->d_flist.ptr;
     lp.nent = int(P.faces.size());
     set_caps(lp, P.caps_face, P.max_nu_face);
     if (adj) {
@@ -937,10 +956,18 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     p->full_u = full.empty() ? 0 : best;
     p->nfull = int(full.size());
     p->nrest = int(rest.size());
+    // launch order of the full blocks: dealt over the XCDs
+    full = deal_over_xcds(full);
     full.insert(full.end(), rest.begin(), rest.end());
     p->h_blist = full;
     if (full.empty()) full.push_back(0);
     HIP_OR_CLEAN(p->d_blist.upload(full, s));
+    // the faces, dealt the same way
+    std::vector<int> faces(P.faces.size());
+    for (size_t i = 0; i < faces.size(); ++i) faces[i] = int(i);
+    faces = deal_over_xcds(faces);
+    if (faces.empty()) faces.push_back(0);
+    HIP_OR_CLEAN(p->d_flist.upload(faces, s));
   }
   {
     // scratch of the wave-level adjoint kernels (entities whose lane plane

@@ -1412,7 +1412,7 @@ template <int NWAVE, int NCMAX, int LMAX>
 __global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
   extern __shared__ double lds[];
   constexpr int BLOCK = NWAVE * 64;
-  const EntDesc& E = a.ents[blockIdx.x];
+  const EntDesc& E = a.ents[ent_index(a)];
   const int nc = E.nc;
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
@@ -1533,7 +1533,7 @@ template <int NCMAX>
 __global__ __launch_bounds__(256) void k_energy_frozen(LocalParams a) {
   constexpr int NQ = NCMAX * (NCMAX + 1) / 2;
   __shared__ double red[4 * NQ];
-  const EntDesc& E = a.ents[blockIdx.x];
+  const EntDesc& E = a.ents[ent_index(a)];
   const int nc = E.nc;
   const int g0 = E.ulo[0] + a.g.s1 * E.ulo[1] + a.g.s2 * E.ulo[2];
   double kacc[NQ];
