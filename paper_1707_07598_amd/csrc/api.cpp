@@ -593,7 +593,7 @@ msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
                           p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
   if (u_out)
     STAGE(MSFV_STAGE_PROLONG,
-          msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns,
+          msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, P.ncv, ns,
                                P.ncell, u_out, p->d_b.ptr, s));
   p->have_forward = true;
   p->basis_ready = true;
@@ -760,7 +760,7 @@ msfv_status jvp_fixed_impl(msfv_problem* p, const double* dm, double* dd_out) {
   const int ns = p->src.count, nr = p->rec.count, nc = int(P.ncoarse);
   HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
   HIP_OK(msfv::launch_check_finite(dm, P.ncell, p->d_status.ptr, s));
-  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, P.ncv, ns, P.ncell,
                               p->d_fu.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_dAu(p->d_m.ptr, dm, p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, s));
   HIP_OK(msfv::launch_restrict(p->d_ccptr.ptr, p->d_ccidx.ptr, p->d_cccell.ptr, p->d_pval.ptr, p->d_fz.ptr,
@@ -785,9 +785,9 @@ msfv_status jtv_fixed_impl(msfv_problem* p, const double* v, double* g_out) {
                                    p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr, p->nrec_slot, ns,
                                    nc, s));
   HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, nullptr, s));
-  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, ns, P.ncell,
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, P.ncv, ns, P.ncell,
                               p->d_fu.ptr, p->d_b.ptr, s));
-  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_lam.ptr, nc, ns, P.ncell,
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_lam.ptr, P.ncv, ns, P.ncell,
                               p->d_fz.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_wfixed(p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, p->d_W.ptr, s));
   HIP_OK(msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));

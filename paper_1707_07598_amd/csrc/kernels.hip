@@ -27,6 +27,7 @@
 //   g_i = sum_{f ni i} dT_f/dm_i W_f.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -1352,16 +1353,33 @@ __global__ void k_transpose_t(const double* __restrict__ t, int nc, int ns, int 
 }
 
 // u_j = S_k t_j for every source: one cell a thread, its S_k row in
-// registers; the coefficients of its corners come four sources at a time
-// from the vertex-major copy (two 16-byte loads per corner), and each
-// source's value is stored coalesced across the wave.
+// registers, each source's value stored coalesced across the wave.  The
+// coefficients come from the vertex-major copy tT (row v: the ldt values of
+// vertex v).  A workgroup's 256 consecutive cells draw on the vertices of at
+// most a few vertex rows J of at most two vertex planes K; when they fit the
+// box of kProlongK planes x kProlongJ rows (and the box fits the dynamic LDS
+// the launch gave), the workgroup stages those rows of tT in LDS with
+// contiguous 16-byte loads and gathers from there instead of through the
+// vector memory path; otherwise it gathers from tT directly.  Either way the
+// sums run in the same order, so u is the same bit for bit.
+constexpr int kProlongK = 2, kProlongJ = 3;
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_prolong(const int* __restrict__ prow, const int* __restrict__ pcol,
                                                  const double* __restrict__ pval, const double* __restrict__ tT,
-                                                 int ldt, int ns, long long ncell, double* __restrict__ u) {
+                                                 int ldt, int ns, int ncx, int ncy, int nc, long long ncell,
+                                                 int staged, double* __restrict__ u) {
+  extern __shared__ double tl[];  // staged: kProlongK * kProlongJ * ncx vertices, ldt + 2 apart
+  __shared__ int red[4][4];
   const long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
-  const int a = prow[cell];
-  const int len = prow[cell + 1] - a;
+  const bool live = cell < ncell;
+  const int a = live ? prow[cell] : 0;
+  const int len = live ? prow[cell + 1] - a : 0;
   int col[8];
   double val[8];
 #pragma unroll
@@ -1369,12 +1387,73 @@ __global__ __launch_bounds__(256) void k_prolong(const int* __restrict__ prow, c
     col[q] = q < len ? pcol[a + q] : 0;
     val[q] = q < len ? pval[a + q] : 0.0;
   }
-  for (int j0 = 0; j0 < ns; j0 += 4) {
+  bool boxed = false;
+  int j0 = 0, k0 = 0;
+  if (staged) {
+    // (min J, -max J, min K, -max K) over the workgroup's columns
+    const int pl = ncx * ncy;
+    int m4[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q >= len) continue;
+      const int K = col[q] / pl, J = (col[q] - K * pl) / ncx;
+      m4[0] = min(m4[0], J);
+      m4[1] = min(m4[1], -J);
+      m4[2] = min(m4[2], K);
+      m4[3] = min(m4[3], -K);
+    }
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m4[i] = wave_min_i(m4[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[wid][i] = m4[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m4[i] = min(min(red[0][i], red[1][i]), min(red[2][i], red[3][i]));
+    j0 = m4[0];
+    k0 = m4[2];
+    // no live column at all (m4 = INT_MAX): nothing to stage, nothing to gather
+    boxed = m4[0] != INT_MAX && -m4[1] - j0 < kProlongJ && -m4[3] - k0 < kProlongK;
+    if (boxed) {
+      // vertex w of the box at tl + w * (ldt + 2): the pad spreads the
+      // vertices a wave reads at once over the LDS banks (ldt is a multiple
+      // of 4, so every vertex stays 16-byte aligned)
+      const int half = ncx * ldt / 2, hv = ldt / 2;
+      for (int e = threadIdx.x; e < kProlongK * kProlongJ * half; e += 256) {
+        const int b = e / half, o = e - b * half;
+        const int kk = b / kProlongJ, jj = b - kk * kProlongJ;
+        const int J = j0 + jj, K = k0 + kk;
+        if (J >= ncy || (K * ncy + J + 1) * ncx > nc) continue;  // past the grid: never read
+        const double2* src = reinterpret_cast<const double2*>(tT + size_t(K * ncy + J) * ncx * ldt);
+        const int w = b * ncx + o / hv, h = o - (o / hv) * hv;
+        reinterpret_cast<double2*>(tl + size_t(w) * (ldt + 2))[h] = src[o];
+      }
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  // position of each column's coefficients (LDS box or tT)
+  const double* base[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (q >= len) {
+      base[q] = tT;  // not read
+    } else if (boxed) {
+      const int pl = ncx * ncy;
+      const int K = col[q] / pl, r = col[q] - K * pl, J = r / ncx, I = r - J * ncx;
+      base[q] = tl + size_t(((K - k0) * kProlongJ + (J - j0)) * ncx + I) * (ldt + 2);
+    } else {
+      base[q] = tT + size_t(col[q]) * ldt;
+    }
+  }
+  for (int jb = 0; jb < ns; jb += 4) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (q < len) {
-        const double2* tp = reinterpret_cast<const double2*>(tT + size_t(col[q]) * ldt + j0);
+        const double2* tp = reinterpret_cast<const double2*>(base[q] + jb);
         const double2 lo = tp[0], hi = tp[1];
         acc[0] += val[q] * lo.x;
         acc[1] += val[q] * lo.y;
@@ -1384,7 +1463,7 @@ __global__ __launch_bounds__(256) void k_prolong(const int* __restrict__ prow, c
     }
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-      if (j0 + jj < ns) u[size_t(j0 + jj) * ncell + cell] = acc[jj];
+      if (jb + jj < ns) u[size_t(jb + jj) * ncell + cell] = acc[jj];
   }
 }
 
@@ -1415,20 +1494,25 @@ __global__ void k_sload(int nelec, const int* ecell, const int* rptr, const int*
 // precomputed: workgroups walk x-rows of cells (xb workgroups a row), so a
 // cell's coordinates come from the workgroup's row without a per-cell
 // division.
+// One workgroup a span of 256 consecutive cells.  Workgroups go round-robin
+// over the eight XCDs (workgroup L to XCD L mod 8), so span = (L mod 8) * spx
+// + L / 8 gives XCD x the contiguous spans [x spx, (x+1) spx): the rows and
+// planes whose sigma and W a span reads around its own cells (i +- n_x,
+// i +- n_x n_y) are then mostly in that XCD's L2, and HBM sees each array
+// about once.
 __global__ __launch_bounds__(256) void k_gfinal(const double* __restrict__ sig, const double* __restrict__ W,
-                                                GridInfo g, long long ncell, int xb, double* __restrict__ grad) {
-  const int row = blockIdx.x / xb;
-  const int x = (blockIdx.x - row * xb) * blockDim.x + threadIdx.x;
-  if (x >= g.n[0]) return;
-  const int y = row % g.n[1], z = row / g.n[1];
-  const long long i = (long long)row * g.n[0] + x;
-  const int c[3] = {x, y, z};
+                                                GridInfo g, int ncell, int spx, double* __restrict__ grad) {
+  const int span = int(blockIdx.x % 8u) * spx + int(blockIdx.x / 8u);
+  const int i = span * 256 + int(threadIdx.x);
+  if (i >= ncell) return;
+  const int row = i / g.n[0];
+  const int c[3] = {i - row * g.n[0], row % g.n[1], row / g.n[1]};
   const double si = sig[i];
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int st = gstride_of(g, k);
-    const double* Wk = W + k * ncell;
+    const double* Wk = W + (long long)k * ncell;
     if (c[k] + 1 < g.n[k]) acc += dharm(si, sig[i + st]) * Wk[i];
     if (c[k] > 0) acc += dharm(si, sig[i - st]) * Wk[i - st];
   }
@@ -1731,12 +1815,16 @@ hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, in
 int prolong_ldt(int ns) { return (std::max(ns, 1) + 3) / 4 * 4; }
 
 hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
-                          int nc, int ns, long long ncell, double* u, double* scratch, hipStream_t s) {
+                          const int ncv[3], int ns, long long ncell, double* u, double* scratch, hipStream_t s) {
   const int ldt = prolong_ldt(ns);
+  const int nc = ncv[0] * ncv[1] * ncv[2];
   const long long nt = (long long)nc * ldt;
   hipLaunchKernelGGL(k_transpose_t, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s, t, nc, ns, ldt, scratch);
-  hipLaunchKernelGGL(k_prolong, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, prow, pcol, pval,
-                     scratch, ldt, ns, ncell, u);
+  // the LDS box of vertex rows, where it fits in 64 KB
+  const size_t box = size_t(kProlongK) * kProlongJ * ncv[0] * (ldt + 2) * sizeof(double);
+  const int staged = box <= 64 * 1024 ? 1 : 0;
+  hipLaunchKernelGGL(k_prolong, dim3(unsigned((ncell + 255) / 256)), dim3(256), staged ? box : 0, s, prow, pcol,
+                     pval, scratch, ldt, ns, ncv[0], ncv[1], nc, ncell, staged, u);
   return hipGetLastError();
 }
 
@@ -1753,10 +1841,11 @@ hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int*
 
 hipError_t launch_gfinal(const double* sig, const double* W, GridInfo g, long long ncell, double* grad,
                          hipStream_t s) {
-  const int rows = int(ncell / g.n[0]);
-  const int xb = (g.n[0] + 255) / 256;
-  hipLaunchKernelGGL(k_gfinal, dim3(unsigned(rows) * unsigned(xb)), dim3(256), 0, s, sig, W, g, ncell, xb,
-                     grad);
+  if (ncell <= 0) return hipSuccess;
+  if (ncell >= (1LL << 31)) return hipErrorInvalidValue;
+  const int spans = int((ncell + 255) / 256);
+  const int spx = (spans + 7) / 8;
+  hipLaunchKernelGGL(k_gfinal, dim3(8u * unsigned(spx)), dim3(256), 0, s, sig, W, g, int(ncell), spx, grad);
   return hipGetLastError();
 }
 

@@ -176,11 +176,12 @@ hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const i
 hipError_t launch_data(const int* rptr, const int* rcell, const double* rval, int nr, int ns,
                        const int* prow, const int* pcol, const double* pval, const double* t,
                        int nc, double* D, hipStream_t s, int accumulate = 0);
-// u_j = S_k t_j (N values per source, column j contiguous); scratch holds
-// nc * prolong_ldt(ns) doubles (the coefficients vertex by vertex)
+// u_j = S_k t_j (N values per source, column j contiguous) on the vertex
+// grid ncv; scratch holds nc * prolong_ldt(ns) doubles (the coefficients
+// vertex by vertex)
 int prolong_ldt(int ns);
 hipError_t launch_prolong(const int* prow, const int* pcol, const double* pval, const double* t,
-                          int nc, int ns, long long ncell, double* u, double* scratch, hipStream_t s);
+                          const int ncv[3], int ns, long long ncell, double* u, double* scratch, hipStream_t s);
 hipError_t launch_sload(int nelec, const int* ecell, const int* rptr, const int* ridx,
                         const double* rw, const int* sptr, const int* sidx, const double* sw,
                         const int* prow, const int* pcol, const double* t, const double* lam,
