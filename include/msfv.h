@@ -113,12 +113,22 @@ typedef struct {
   long long pairs_face;  /* the same for the faces (3-D) or 2-D blocks      */
 } msfv_sizes;
 
+/* The local-solve figures (iteration count, final residual) cover the
+ * basis solves of the last forward and the adjoint solves of the J^T v
+ * after it; the other counters run since the last forward, msfv_jvp or
+ * msfv_jvp_fixed (each of these resets them; msfv_jtv and msfv_jtv_fixed add
+ * to them).  Residuals are relative, ||r|| /
+ * ||b|| of a solve's final iterate (local solves on the Jacobi-scaled local
+ * system; coarse solves on the pinned Galerkin system); +inf marks a solve
+ * that produced a non-finite residual.                                     */
 typedef struct {
-  int local_max_it;       /* largest local CG iteration count, last call     */
-  int local_noconv;       /* local solves that hit the cap, last call        */
-  int coarse_max_it;      /* largest coarse CG iteration count, last call    */
-  int coarse_noconv;      /* coarse solves that hit the cap, last call       */
+  int local_max_it;       /* largest local CG iteration count                */
+  int local_noconv;       /* local solves that hit the cap                   */
+  int coarse_max_it;      /* largest coarse CG iteration count               */
+  int coarse_noconv;      /* coarse solves that hit the cap                  */
   int nonfinite;          /* 1 if m contained NaN/Inf                        */
+  double local_max_res;   /* largest final relative residual, local solves  */
+  double coarse_max_res;  /* the same for the coarse solves                  */
 } msfv_stats;
 
 /* Create a problem for one grid; builds the plan (entity tables, CSR
@@ -220,6 +230,9 @@ msfv_status msfv_sync(msfv_problem* p);
 msfv_status msfv_get_sizes(msfv_problem* p, msfv_sizes* out);
 msfv_status msfv_get_prolongation(msfv_problem* p, int* row_ptr, int* col, double* val);
 msfv_status msfv_get_coarse(msfv_problem* p, int* row_ptr, int* col, double* val, double* t_out);
+/* Iteration counts, cap hits and final relative residuals of the local
+ * (Sec. 3.2, eq. multiscaleBasis_step3) and coarse (eq. reducedPDE) solves
+ * (struct above); synchronises the problem's stream. */
 msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out);
 
 /* Stage profiling.  When enabled, every stage launched by msfv_forward,

@@ -60,7 +60,8 @@ class MsfvServeStats(ctypes.Structure):
 class MsfvStats(ctypes.Structure):
     _fields_ = [("local_max_it", ctypes.c_int), ("local_noconv", ctypes.c_int),
                 ("coarse_max_it", ctypes.c_int), ("coarse_noconv", ctypes.c_int),
-                ("nonfinite", ctypes.c_int)]
+                ("nonfinite", ctypes.c_int), ("local_max_res", ctypes.c_double),
+                ("coarse_max_res", ctypes.c_double)]
 
 
 NSTAGE = 19

@@ -139,6 +139,7 @@ struct msfv_problem {
   // per-entity CG statistics of the four local stages (block fwd, block adj,
   // face fwd, face adj), at offsets ent_off[slot]
   DevBuf<int> d_ent_it;
+  DevBuf<double> d_ent_res;  // 8 slots an entity: final (||r|| / ||b||)^2 of its local solves
   DevBuf<unsigned long long> d_ent_work;
   int ent_off[5] = {0, 0, 0, 0, 0};
   // two-level coarse preconditioner: aggregates and (Z^T A_k Z)^-1
@@ -418,6 +419,7 @@ msfv::LocalParams base_params(msfv_problem* p) {
 // 1 block adj, 2 face fwd, 3 face adj).
 void set_stats(msfv_problem* p, msfv::LocalParams& lp, int slot) {
   lp.ent_it = p->d_ent_it.ptr + p->ent_off[slot];
+  lp.ent_res = p->d_ent_res.ptr + size_t(8) * p->ent_off[slot];
   lp.ent_work = p->prof.on ? p->d_ent_work.ptr + p->ent_off[slot] : nullptr;
 }
 
@@ -535,6 +537,7 @@ msfv_status fwd_begin(msfv_problem* p, const double* m) {
   hipStream_t s = p->stream;
   HIP_OK(msfv::launch_zero(p->d_status.ptr, sizeof(int) * msfv::kStCount, s));
   HIP_OK(msfv::launch_zero(p->d_ent_it.ptr, p->d_ent_it.bytes(), s));
+  HIP_OK(msfv::launch_zero(p->d_ent_res.ptr, p->d_ent_res.bytes(), s));
   STAGE(MSFV_STAGE_COPY_M,
         msfv::launch_prep_model(p->d_m.ptr, p->d_sig.ptr, m, P.ncell, p->d_status.ptr, s));
   return MSFV_OK;
@@ -989,8 +992,10 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     const int cnt[4] = {nb, nb, nf, nf};
     for (int k = 0; k < 4; ++k) p->ent_off[k + 1] = p->ent_off[k] + cnt[k];
     HIP_OR_CLEAN(p->d_ent_it.alloc(std::max(1, p->ent_off[4])));
+    HIP_OR_CLEAN(p->d_ent_res.alloc(size_t(8) * std::max(1, p->ent_off[4])));
     HIP_OR_CLEAN(p->d_ent_work.alloc(std::max(1, p->ent_off[4])));
     HIP_OR_CLEAN(hipMemsetAsync(p->d_ent_it.ptr, 0, p->d_ent_it.bytes(), s));
+    HIP_OR_CLEAN(hipMemsetAsync(p->d_ent_res.ptr, 0, p->d_ent_res.bytes(), s));
     HIP_OR_CLEAN(hipMemsetAsync(p->d_ent_work.ptr, 0, p->d_ent_work.bytes(), s));
   }
   HIP_OR_CLEAN(hipMemsetAsync(p->d_work.ptr, 0, p->d_work.bytes(), s));
@@ -1254,6 +1259,20 @@ msfv_status msfv_get_stats(msfv_problem* p, msfv_stats* out) {
   out->coarse_max_it = st[msfv::kStCoarseMaxIt];
   out->coarse_noconv = st[msfv::kStCoarseNoconv];
   out->nonfinite = st[msfv::kStNonfinite];
+  auto res = [&](int slot) {
+    unsigned long long bits;
+    std::memcpy(&bits, st + slot, sizeof bits);
+    double v;
+    std::memcpy(&v, &bits, sizeof v);
+    return std::sqrt(v);
+  };
+  std::vector<double> lr(p->d_ent_res.n);
+  if (!lr.empty())
+    HIP_OK(hipMemcpy(lr.data(), p->d_ent_res.ptr, p->d_ent_res.bytes(), hipMemcpyDeviceToHost));
+  double lmax = 0.0;
+  for (double v : lr) lmax = (v >= 0.0) ? std::max(lmax, v) : HUGE_VAL;  // a NaN counts as +inf
+  out->local_max_res = std::sqrt(lmax);
+  out->coarse_max_res = res(msfv::kStCoarseRes);
   return MSFV_OK;
 }
 

@@ -322,6 +322,14 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   block_sum<NW, 2>(s0, redA);  // its barrier also orders the staging reads before the writes below
   const double bb = s0[0];
   double rz = s0[1];
+  // r.r of the current iterate, kept in scalar registers (the value is the
+  // same in every lane)
+  auto uniform = [](double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+  };
+  double last = uniform(bb);
   bool done = !(bb > 0.0);
   const double tol2 = rtol * rtol;
   const bool owns_pin = threadIdx.x == 0;
@@ -427,6 +435,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
       s2[1] += r[q] * zrow(q);
     }
     block_sum<NW, 2>(s2, redB);
+    last = uniform(s2[0]);
     if (s2[0] <= tol2 * bb) break;
     if (s2[0] != s2[0]) {
       ok = false;
@@ -449,6 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   if (threadIdx.x == 0) {
     atomicMax(status + kStCoarseMaxIt, it);
     if (!ok) atomicAdd(status + kStCoarseNoconv, 1);
+    if (bb > 0.0) note_residual(status, kStCoarseRes, last / bb);
     if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
   }
 }
@@ -793,6 +803,8 @@ __global__ __launch_bounds__(kMT) void k_cgm_pupdate(const double* __restrict__ 
     if (stop) {
       atomicMax(status + kStCoarseMaxIt, it);
       if (bad) atomicAdd(status + kStCoarseNoconv, 1);
+      const double b2 = S.scal[3 * j + 2];
+      if (b2 > 0.0) note_residual(status, kStCoarseRes, rr / b2);
       if (work) atomicAdd(work, (unsigned long long)it * (unsigned long long)nc);
     }
   }

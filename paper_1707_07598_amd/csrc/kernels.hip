@@ -191,7 +191,7 @@ template <int BLOCK, int CPT, int NCP>
 __device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], const double* tp, int ncp,
                          const double (&b)[CPT][NCP], double (&x)[CPT][NCP], double* pb,
                          double* redA, double* redB, double tol2, int maxit, bool* ok,
-                         const double (*x0)[CPT][NCP] = nullptr) {
+                         const double (*x0)[CPT][NCP] = nullptr, double* res2 = nullptr) {
   constexpr int NW = BLOCK / kWave;
   const int nu = E.nu;
   double r[CPT][NCP], pv[CPT][NCP];
@@ -368,6 +368,18 @@ __device__ int local_pcg(const EntDesc& E, const CellGeo (&cg)[CPT], const doubl
     }
     __syncthreads();
   }
+  if (res2) {
+    // (||r|| / ||b||)^2 of the worst column: sums holds the last r.r
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCP; ++c)
+      if (c < ncp && bb[c] > 0.0) {
+        double q = sums[c] / bb[c];
+        if (!(q >= 0.0)) q = __builtin_huge_val();
+        m2 = fmax(m2, q);
+      }
+    *res2 = m2;
+  }
   return it;
 }
 
@@ -452,6 +464,7 @@ __device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, do
   int itmax = 0;
   unsigned long long work = 0;
   bool all_ok = true;
+  double resmax = 0.0;
   // faces (and 2-D dual blocks) bounded by vertex planes on both open axes
   // start their solves from the interpolation of the boundary values (8
   // lookups a cell; for 15^3 dual blocks the 26 lookups a cell cost more
@@ -487,6 +500,7 @@ __device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, do
       __syncthreads();  // previous pass finished with the LDS buffers
       bool ok = true;
       int it;
+      double res2 = 0.0;
       if (guess) {
         // start from the interpolation of the boundary values
         double x0[CPT][NCP];
@@ -500,10 +514,12 @@ __device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, do
           for (int c = 0; c < NCP; ++c)
             if (c < ncp) x0[j][c] = coons_value(E, a.g, a.prow, a.pcol, a.pval, own, E.vid[c0 + c]);
         }
-        it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok, &x0);
+        it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok, &x0, &res2);
       } else {
-        it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+        it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok, nullptr,
+                                        &res2);
       }
+      resmax = fmax(resmax, res2);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
       work += (unsigned long long)it * E.nu * ncp;
@@ -523,6 +539,7 @@ __device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, do
       a.ent_it[eid] = itmax;
       if (a.ent_work) a.ent_work[eid] += work;
     }
+    if (a.ent_res) a.ent_res[size_t(eid) * 8] = resmax;
   }
   __syncthreads();  // S_k rows of this entity are visible to the workgroup
 
@@ -894,11 +911,13 @@ __device__ __forceinline__ void local_adj_body(const LocalParams& a, int eid, do
       }
     }
     if (threadIdx.x == 0 && a.ent_it) a.ent_it[eid] = 0;
+    if (threadIdx.x == 0 && a.ent_res) a.ent_res[size_t(eid) * 8] = 0.0;
   } else if (a.solve_adj) {
     const double tol2 = a.rtol * a.rtol;
     int itmax = 0;
     unsigned long long work = 0;
     bool all_ok = true;
+    double resmax = 0.0;
     for (int c0 = 0; c0 < nc; c0 += NCP) {
       const int ncp = min(NCP, nc - c0);
       double b[CPT][NCP], x[CPT][NCP];
@@ -908,7 +927,10 @@ __device__ __forceinline__ void local_adj_body(const LocalParams& a, int eid, do
         for (int c = 0; c < NCP; ++c) b[j][c] = (c < ncp) ? zh[j][c0 + c] : 0.0;
       __syncthreads();
       bool ok = true;
-      const int it = local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok);
+      double res2 = 0.0;
+      const int it =
+          local_pcg<BLOCK, CPT, NCP>(E, cg, tp, ncp, b, x, pb, redA, redB, tol2, a.maxit, &ok, nullptr, &res2);
+      resmax = fmax(resmax, res2);
       itmax = max(itmax, it);
       all_ok = all_ok && ok;
       work += (unsigned long long)it * E.nu * ncp;
@@ -981,6 +1003,7 @@ __device__ __forceinline__ void local_adj_body(const LocalParams& a, int eid, do
         a.ent_it[eid] = itmax;
         if (a.ent_work) a.ent_work[eid] += work;
       }
+      if (a.ent_res) a.ent_res[size_t(eid) * 8] = resmax;
     }
   }
   // flux weights of the fluxes this entity owns

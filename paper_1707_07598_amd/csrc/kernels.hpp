@@ -24,8 +24,19 @@ enum StatusSlot {
   kStReserved = 2,  // local CG iteration counts are kept per entity
   kStCoarseNoconv = 3,
   kStCoarseMaxIt = 4,
+  kStCoarseRes = 6,  // two words: largest (||r|| / ||b||)^2 of a coarse solve, as double bits
   kStCount = 8
 };
+
+// Raise the residual maximum in status[slot] to rel2 = (||r|| / ||b||)^2 of
+// a finished solve.  The bit patterns of non-negative doubles order like
+// their values, so an unsigned 64-bit maximum keeps the largest; a NaN
+// counts as +inf.
+__device__ __forceinline__ void note_residual(int* status, int slot, double rel2) {
+  if (!(rel2 >= 0.0)) rel2 = __builtin_huge_val();
+  atomicMax(reinterpret_cast<unsigned long long*>(status + slot),
+            static_cast<unsigned long long>(__double_as_longlong(rel2)));
+}
 
 struct LocalParams {
   const EntDesc* ents = nullptr;  // entities solved by this launch
@@ -62,6 +73,7 @@ struct LocalParams {
   int solve_adj = 1;               // 0: flux-derivative (G) term only
   int push = 1;                    // 1: push loads to lower entities
   int* ent_it = nullptr;                  // per entity: largest CG iteration count of its corners
+  double* ent_res = nullptr;              // per entity, 8 slots (corners or passes): final (||r|| / ||b||)^2
   unsigned long long* ent_work = nullptr; // per entity, if set: += CG cell-iterations (iterations x own cells)
   double* mu_scratch = nullptr;           // adjoint: per entity 8 * nu_cap doubles (local adjoint solutions)
   int uni_cap = 0;                        // wave kernels: doubles of the shared plane-buffer region

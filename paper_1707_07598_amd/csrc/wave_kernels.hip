@@ -374,7 +374,7 @@ __device__ __forceinline__ void load_column(const EntDesc& E, const WGeo& w, boo
 template <int LMAX>
 __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
                        double (&y)[LMAX], double* pbuf, double tol2, int maxit, bool* ok,
-                       const double (*x0)[LMAX] = nullptr) {
+                       const double (*x0)[LMAX] = nullptr, double* res2 = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < w.plane * w.L; i += kWave) pbuf[i] = 0.0;
   wave_sync_lds();
@@ -393,6 +393,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
   const double bb = rr;
   int it = 0;
   *ok = true;
+  if (res2) *res2 = 0.0;
   if (!(bb > 0.0)) return 0;
   if (x0) {
     // r = y - A x0 (the in-plane neighbours of x0 through the plane buffer)
@@ -417,8 +418,12 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
     }
     rr = wsum(rr);
     wave_sync_lds();  // all lanes finished reading x0 before the loop writes p
-    if (rr <= tol2 * bb) return 0;
+    if (rr <= tol2 * bb) {
+      if (res2) *res2 = rr / bb;
+      return 0;
+    }
   }
+  double last = rr;  // r.r of the current iterate
   while (true) {
     if (it >= maxit) {
       *ok = false;
@@ -457,6 +462,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
       rn += r[k] * r[k];
     }
     rn = wsum(rn);
+    last = rn;
     if (rn <= tol2 * bb) break;
     if (rn != rn) {
       *ok = false;
@@ -468,6 +474,7 @@ __device__ int wave_cg(const WGeo& w, bool valid, int ia, int ib, const Column<L
     for (int k = 0; k < LMAX; ++k) p[k] = r[k] + beta * p[k];
     wave_sync_lds();  // all lanes finished reading the previous directions
   }
+  if (res2) *res2 = last / bb;
   return it;
 }
 
@@ -514,7 +521,8 @@ __device__ __forceinline__ void reduce4(double (&v)[4]) {
 template <int LMAX>
 __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column<LMAX>& C,
                          double (&y)[4][LMAX], double* buf, int plane_cap, double tol2, int maxit,
-                         int (&its)[4], bool (&ok)[4], const double (*x0)[4][LMAX] = nullptr) {
+                         int (&its)[4], bool (&ok)[4], const double (*x0)[4][LMAX] = nullptr,
+                         double* res2 = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < 4 * plane_cap; i += kWave) buf[i] = 0.0;
   wave_sync_lds();
@@ -533,9 +541,11 @@ __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column
     }
   }
   reduce4(rr);
+  double last[4];  // r.r of each corner's current iterate
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     bb[c] = rr[c];
+    last[c] = rr[c];
     done[c] = !(bb[c] > 0.0);
     its[c] = 0;
     ok[c] = true;
@@ -571,6 +581,7 @@ __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column
     reduce4(rr);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+      last[c] = rr[c];
       if (!done[c] && rr[c] <= tol2 * bb[c]) {
         done[c] = true;
 #pragma unroll
@@ -627,6 +638,7 @@ __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column
     reduce4(rn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+      last[c] = rn[c];
       double be = 0.0;
       if (!done[c]) {
         if (rn[c] <= tol2 * bb[c]) {
@@ -646,6 +658,17 @@ __device__ void wave_cg4(const WGeo& w, bool valid, int ia, int ib, const Column
       for (int k = 0; k < LMAX; ++k) p[c][k] = done[c] ? 0.0 : r[c][k] + be * p[c][k];
     }
     wave_sync_lds();  // all lanes finished reading the previous directions
+  }
+  if (res2) {
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (bb[c] > 0.0) {
+        double q = last[c] / bb[c];
+        if (!(q >= 0.0)) q = __builtin_huge_val();
+        m2 = fmax(m2, q);
+      }
+    *res2 = m2;
   }
 }
 
@@ -895,13 +918,16 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
       }
       int its[4];
       bool ok[4];
+      double res2 = 0.0;
       if (guess2) {
         double x0[4][LMAX];
 #pragma unroll
         for (int c = 0; c < 4; ++c) coons2(c, ia0, ib0, x0[c]);
-        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok, &x0);
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok, &x0,
+                       &res2);
       } else {
-        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok, nullptr,
+                       &res2);
       }
       if (lane == 0) {
 #pragma unroll
@@ -910,6 +936,7 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
           S.wit[c] = its[c];
           if (!ok[c]) atomicAdd(a.status + kStLocalNoconv, 1);
         }
+        if (a.ent_res) a.ent_res[size_t(eid) * 8] = res2;
       }
     }
 #pragma unroll
@@ -928,16 +955,18 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
         rhs(c, ia, ib, y);
         bool ok = true;
         int it;
+        double res2 = 0.0;
         if (guess) {
           double x0[LMAX];
           coons(c, ia, ib, x0);
-          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok, &x0);
+          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok, &x0, &res2);
         } else {
-          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok);
+          it = wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok, nullptr, &res2);
         }
         if (lane == 0) {
           S.wit[c] = it;
           if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+          if (a.ent_res) a.ent_res[size_t(eid) * 8 + c] = res2;
         }
         wave_sync_lds();
       }
@@ -1206,8 +1235,10 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
       __threadfence_block();  // the y-part stores complete before the mu-part adds below
       int its[4] = {0, 0, 0, 0};
       bool ok[4] = {true, true, true, true};
+      double res2 = 0.0;
       if (loaded)
-        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok);
+        wave_cg4<LMAX>(w, valid, ia0, ib0, C, y, S.pbuf, a.plane_cap, a.rtol * a.rtol, a.maxit, its, ok, nullptr,
+                       &res2);
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -1215,6 +1246,7 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
           S.wit[c] = its[c];
           if (!ok[c]) atomicAdd(a.status + kStLocalNoconv, 1);
         }
+        if (a.ent_res) a.ent_res[size_t(eid) * 8] = res2;
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c)
@@ -1277,10 +1309,13 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
       }
       __threadfence_block();  // the y-part stores complete before the mu-part adds below
       bool ok = true;
-      const int it = loaded ? wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok) : 0;
+      double res2 = 0.0;
+      const int it =
+          loaded ? wave_cg<LMAX>(w, valid, ia, ib, C, y, pbuf, a.rtol * a.rtol, a.maxit, &ok, nullptr, &res2) : 0;
       if (lane == 0) {
         S.wit[c] = it;
         if (!ok) atomicAdd(a.status + kStLocalNoconv, 1);
+        if (a.ent_res) a.ent_res[size_t(eid) * 8 + c] = res2;
       }
       // mu_c to the scratch; mu-part of the pushes.  A zero load (no
       // electrodes, no pushes from above) gives mu_c = 0 without iterations:

@@ -226,6 +226,35 @@ def test_determinism_and_stats():
     prob.close()
 
 
+@pytest.mark.parametrize("precond", ["twolevel", "multi"])
+def test_residual_stats(precond):
+    """msfv_get_stats reports the final relative residuals of the local and
+    coarse solves: within the stop tolerance (1e-13) when every solve
+    converged, above it (with the cap hits counted) when the caps cut the
+    iterations short."""
+    torch = _torch()
+    import paper_1707_07598_amd as msfv
+    n, r = (13, 11, 9), (4, 4, 4)
+    inst = W.small_instance(n, r, seed=17, ns=2, nr=3)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    v = torch.ones((2, 3), dtype=torch.float64, device="cuda")
+    prob = _problem(n, r, "reduced", inst, coarse_precond=precond)
+    prob.forward(m)
+    prob.jtv(v)
+    s = prob.stats()
+    assert s.local_noconv == 0 and s.coarse_noconv == 0
+    assert 0.0 < s.local_max_res <= 1e-13 and 0.0 < s.coarse_max_res <= 1e-13
+    prob.close()
+    capped = _problem(n, r, "reduced", inst, coarse_precond=precond, local_maxit=2, coarse_maxit=3)
+    with pytest.raises(msfv.MsfvError):
+        capped.forward(m)
+    s = capped.stats()
+    assert s.local_noconv > 0 and s.coarse_noconv > 0
+    assert s.local_max_res > 1e-13 and s.coarse_max_res > 1e-13
+    assert np.isfinite(s.local_max_res) and np.isfinite(s.coarse_max_res)
+    capped.close()
+
+
 def test_error_paths():
     torch = _torch()
     import paper_1707_07598_amd as msfv
