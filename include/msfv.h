@@ -160,6 +160,15 @@ msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double
  * transposed): v device Nr*Ns (same layout as D), g_out device N. */
 msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out);
 
+/* msfv_forward(m, d_out, NULL) followed by msfv_jtv(v, g_out), for a v that
+ * is known before the forward (it is not derived from this D): the adjoint
+ * coarse problem A_k lambda_j = S_k^T Rx v_j (Sec. 4.3) needs only A_k, S_k
+ * and v, so it is solved in the same coarse launch as the forward's A_k t_j
+ * = S_k^T q_j (eq. fwdProbRed), 2 Ns columns at once.  Same arguments,
+ * results (bit for bit) and errors as the two calls. */
+msfv_status msfv_forward_jtv(msfv_problem* p, const double* m, const double* v, double* d_out,
+                             double* g_out);
+
 /* Forward-mode sensitivity J_k(m) dm at the m of the last msfv_forward
  * (Sec. 4.3 eq. sensred applied to dm, with the tangent of the adaptive basis
  * of Sec. 4.5): dD = Rx^T (dS_k t + S_k dt), A_k dt = dS_k^T q - dA_k t, where

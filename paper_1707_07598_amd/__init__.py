@@ -155,6 +155,24 @@ class Problem:
             self.sync()
         return (D, u) if want_u else D
 
+    def forward_jtv(self, m, v, sync: bool = True):
+        """(D, g): the forward at m and g = J_k(m)^T v for a v known before
+        the forward, with both coarse problems solved in one launch; the
+        same results as ``forward(m)`` then ``jtv(v)``."""
+        torch = _torch()
+        ncell = int(np.prod(self.n))
+        self._check_tensor(m, ncell, "m")
+        self._check_tensor(v, self._ns * self._nr, "v")
+        D = torch.empty((self._ns, self._nr), dtype=torch.float64, device=m.device)
+        g = torch.empty(ncell, dtype=torch.float64, device=m.device)
+        _lib.check(self.lib.msfv_forward_jtv(self._h, _dptr(m), _dptr(v), _dptr(D), _dptr(g)),
+                   "msfv_forward_jtv")
+        self.generation += 1
+        self.last_m = m
+        if sync:
+            self.sync()
+        return D, g
+
     def jtv(self, v, out=None, sync: bool = True):
         """g = J_k(m)^T v at the m of the last forward; v is (Ns, Nr)."""
         torch = _torch()

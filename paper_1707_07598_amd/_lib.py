@@ -85,6 +85,7 @@ SIGNATURES = {
     "msfv_set_receivers": (_I, [_P, _I, _IP, _IP, _DP]),
     "msfv_forward": (_I, [_P, _P, _P, _P]),
     "msfv_jtv": (_I, [_P, _P, _P]),
+    "msfv_forward_jtv": (_I, [_P, _P, _P, _P, _P]),
     "msfv_misfit_grad": (_I, [_P, _P, _P, _P, _P]),
     "msfv_misfit_grad_noalloc": (_I, [_P, _P, _P, _P, _P]),
     "msfv_jvp": (_I, [_P, _P, _P]),

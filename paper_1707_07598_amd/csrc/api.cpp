@@ -134,7 +134,10 @@ struct msfv_problem {
   int nelec = 0, nsrc_slot = 0, nrec_slot = 0;
 
   // coarse vectors (column j contiguous) and data scratch
-  DevBuf<double> d_b, d_t, d_lam, d_D, d_v;
+  // d_t holds t (Nc x Ns) followed by lambda (Nc x Ns), so that forward and
+  // adjoint coarse problems can be solved in one launch of 2 Ns columns;
+  // d_b holds their right-hand sides in the same order
+  DevBuf<double> d_b, d_t, d_D, d_v;
   DevBuf<unsigned long long> d_work;
   // per-entity CG statistics of the four local stages (block fwd, block adj,
   // face fwd, face adj), at offsets ent_off[slot]
@@ -170,7 +173,7 @@ struct msfv_problem {
            d_krow.bytes() + d_kcol.bytes() + d_kcptr.bytes() + d_kcidx.bytes() + d_kdslot.bytes() +
            d_vrows.bytes() + d_pval.bytes() + d_kval.bytes() + d_kdia.bytes() + d_kent.bytes() +
            d_inbuf.bytes() + d_W.bytes() +
-           d_m.bytes() + d_sig.bytes() + d_b.bytes() + d_t.bytes() + d_lam.bytes() + d_D.bytes() + d_v.bytes() +
+           d_m.bytes() + d_sig.bytes() + d_b.bytes() + d_t.bytes() + d_D.bytes() + d_v.bytes() +
            d_sload.bytes() + d_einv.bytes() + d_arows.bytes() + d_cg_ws.bytes() + d_mu.bytes() + d_dpval.bytes() +
            d_dkent.bytes() + d_dkval.bytes() + d_dkdia.bytes() + d_dt.bytes() + d_fu.bytes() +
            d_fz.bytes() + d_ccptr.bytes() + d_ccidx.bytes() + d_cccell.bytes();
@@ -351,19 +354,20 @@ msfv_status build_electrodes(msfv_problem* p) {
   HIP_OK(p->d_rval.upload(p->rec.val.empty() ? std::vector<double>{0.0} : p->rec.val, s));
   // coarse vectors
   const size_t ncs = size_t(nc) * std::max(1, ns);
-  HIP_OK(p->d_b.alloc(size_t(nc) * msfv::prolong_ldt(ns)));  // also the prolongation's scratch
-  HIP_OK(p->d_t.alloc(ncs));
-  HIP_OK(p->d_lam.alloc(ncs));
+  // also the prolongation's scratch
+  HIP_OK(p->d_b.alloc(std::max(size_t(nc) * msfv::prolong_ldt(ns), 2 * ncs)));
+  HIP_OK(p->d_t.alloc(2 * ncs));
   HIP_OK(p->d_D.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
   HIP_OK(p->d_v.alloc(size_t(std::max(1, nr)) * std::max(1, ns)));
   if (coarse_multi(p)) {
-    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, std::max(1, ns)) / sizeof(double) + 1));
-    if (p->flags_cap < ns) {  // grow only: freeing pinned memory synchronises the device
+    // room for the 2 Ns columns of a forward + adjoint solve
+    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, 2 * std::max(1, ns)) / sizeof(double) + 1));
+    if (p->flags_cap < 2 * ns) {  // grow only: freeing pinned memory synchronises the device
       if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
       p->h_flags = nullptr;
       p->flags_cap = 0;
-      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * std::max(1, ns)));
-      p->flags_cap = std::max(1, ns);
+      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * 2 * std::max(1, ns)));
+      p->flags_cap = 2 * std::max(1, ns);
     }
   }
   HIP_OK(hipStreamSynchronize(s));  // host vectors above are temporaries
@@ -371,6 +375,9 @@ msfv_status build_electrodes(msfv_problem* p) {
   ++p->generation;
   return MSFV_OK;
 }
+
+// lambda (the adjoint coarse coefficients) sits after t in d_t
+double* lam_ptr(msfv_problem* p) { return p->d_t.ptr + size_t(p->plan.ncoarse) * std::max(1, p->src.count); }
 
 // Workgroups go round-robin over the eight XCDs (workgroup k to XCD k mod 8),
 // each with its own L2.  The launch order of a list of entities deals them so
@@ -403,7 +410,7 @@ msfv::LocalParams base_params(msfv_problem* p) {
   lp.status = p->d_status.ptr;
   lp.sig_cap = p->plan.max_closure;
   lp.t = p->d_t.ptr;
-  lp.lam = p->d_lam.ptr;
+  lp.lam = lam_ptr(p);
   lp.ncoarse = int(p->plan.ncoarse);
   lp.ns = p->src.count;
   lp.inbuf = p->d_inbuf.ptr;
@@ -433,14 +440,16 @@ void set_caps(msfv::LocalParams& lp, const msfv::Plan::Caps& c, int nu_cap) {
 }
 
 // Coarse solves of the ns columns of rhs with the configured preconditioner.
+// ncol columns (default: one a source), column j at rhs + j Nc and x + j Nc
 hipError_t coarse_solve(msfv_problem* p, const double* rhs, double* x, unsigned long long* work,
-                        hipStream_t s) {
+                        hipStream_t s, int ncol = -1) {
   const msfv::Plan& P = p->plan;
+  if (ncol < 0) ncol = p->src.count;
   if (coarse_multi(p))
-    return msfv::launch_coarse_pcg_large(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
+    return msfv::launch_coarse_pcg_large(p->d_kdia.ptr, P.ncv, rhs, x, ncol, p->cfg.coarse_rtol,
                                          p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
                                          p->d_cg_ws.ptr, p->h_flags, p->d_status.ptr, work, s);
-  return msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, rhs, x, p->src.count, p->cfg.coarse_rtol,
+  return msfv::launch_coarse_pcg(p->d_kdia.ptr, P.ncv, rhs, x, ncol, p->cfg.coarse_rtol,
                                  p->cfg.coarse_maxit, p->defl.ok ? &p->defl : nullptr,
                                  p->d_status.ptr, work, s);
 }
@@ -572,7 +581,9 @@ msfv_status fwd_local(msfv_problem* p) {
   return MSFV_OK;
 }
 
-msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
+// Galerkin operator, coarse preconditioner and the forward right-hand sides
+// S_k^T q_j (columns 0 .. Ns-1 of d_b); ncol_zero columns of d_b cleared.
+msfv_status coarse_prep(msfv_problem* p, int ncol_zero) {
   const msfv::Plan& P = p->plan;
   hipStream_t s = p->stream;
   STAGE(MSFV_STAGE_KASSEMBLE,
@@ -582,15 +593,21 @@ msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
     STAGE(MSFV_STAGE_COARSE_SETUP,
           msfv::launch_coarse_defl_setup(p->d_kdia.ptr, P.ncv, p->defl, p->d_einv.ptr,
                                          p->d_status.ptr, s));
-  const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
-  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ncol_zero, s));
   STAGE(MSFV_STAGE_COARSE_RHS,
         msfv::launch_gather_slots(p->d_src_dst.ptr, p->d_src_ptr.ptr, p->d_src_pidx.ptr,
                                   p->d_src_w.ptr, nullptr, nullptr, 0, p->d_pval.ptr, p->d_b.ptr,
                                   p->nsrc_slot, 1, nc, s));
-  STAGE(MSFV_STAGE_COARSE_FWD,
-        coarse_solve(p, p->d_b.ptr, p->d_t.ptr, p->d_work.ptr + 4, s));
+  return MSFV_OK;
+}
+
+// D = Rx^T S_k t (and u = S_k t) from the solved t
+msfv_status fwd_data(msfv_problem* p, double* d_out, double* u_out) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const int ns = p->src.count, nr = p->rec.count;
+  const int nc = int(P.ncoarse);
   STAGE(MSFV_STAGE_DATA,
         msfv::launch_data(p->d_rptr.ptr, p->d_rcell.ptr, p->d_rval.ptr, nr, ns, p->d_prow.ptr,
                           p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, nc, d_out, s));
@@ -603,6 +620,15 @@ msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
   return MSFV_OK;
 }
 
+msfv_status fwd_end(msfv_problem* p, double* d_out, double* u_out) {
+  hipStream_t s = p->stream;
+  msfv_status st = coarse_prep(p, p->src.count);
+  if (st != MSFV_OK) return st;
+  STAGE(MSFV_STAGE_COARSE_FWD,
+        coarse_solve(p, p->d_b.ptr, p->d_t.ptr, p->d_work.ptr + 4, s));
+  return fwd_data(p, d_out, u_out);
+}
+
 msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double* u_out) {
   msfv_status st = fwd_begin(p, m);
   if (st == MSFV_OK) st = fwd_local(p);
@@ -612,24 +638,62 @@ msfv_status forward_impl(msfv_problem* p, const double* m, double* d_out, double
 
 // J^T v in three parts: the adjoint coarse problem and the direct electrode
 // loads, the local adjoint sweeps (blocks, faces, edges), and g.
-msfv_status adj_begin(msfv_problem* p, const double* v) {
-  if (!p->have_forward) return fail(MSFV_ESTATE, "msfv_jtv called before msfv_forward");
+// The adjoint right-hand sides S_k^T Rx v_j into rhs (Ns columns, cleared
+// by the caller).
+msfv_status adj_rhs(msfv_problem* p, const double* v, double* rhs) {
   const msfv::Plan& P = p->plan;
   hipStream_t s = p->stream;
   const int ns = p->src.count, nr = p->rec.count;
   const int nc = int(P.ncoarse);
-  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * ns, s));
   STAGE(MSFV_STAGE_ADJ_RHS,
         msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr,
-                                  p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr,
+                                  p->d_rec_w.ptr, p->d_rec_col.ptr, v, nr, p->d_pval.ptr, rhs,
                                   p->nrec_slot, ns, nc, s));
-  STAGE(MSFV_STAGE_COARSE_ADJ,
-        coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, p->d_work.ptr + 5, s));
+  return MSFV_OK;
+}
+
+msfv_status adj_sload(msfv_problem* p, const double* v) {
+  const msfv::Plan& P = p->plan;
+  hipStream_t s = p->stream;
+  const int ns = p->src.count, nr = p->rec.count;
+  const int nc = int(P.ncoarse);
   STAGE(MSFV_STAGE_SLOAD,
         msfv::launch_sload(p->nelec, p->d_ecell.ptr, p->d_erptr.ptr, p->d_eridx.ptr, p->d_erw.ptr,
                            p->d_esptr.ptr, p->d_esidx.ptr, p->d_esw.ptr, p->d_prow.ptr, p->d_pcol.ptr,
-                           p->d_t.ptr, p->d_lam.ptr, v, nc, ns, nr, p->d_sload.ptr, s));
+                           p->d_t.ptr, lam_ptr(p), v, nc, ns, nr, p->d_sload.ptr, s));
   return MSFV_OK;
+}
+
+msfv_status adj_begin(msfv_problem* p, const double* v) {
+  if (!p->have_forward) return fail(MSFV_ESTATE, "msfv_jtv called before msfv_forward");
+  hipStream_t s = p->stream;
+  const int nc = int(p->plan.ncoarse);
+  HIP_OK(msfv::launch_zero(p->d_b.ptr, sizeof(double) * size_t(nc) * p->src.count, s));
+  msfv_status st = adj_rhs(p, v, p->d_b.ptr);
+  if (st != MSFV_OK) return st;
+  STAGE(MSFV_STAGE_COARSE_ADJ,
+        coarse_solve(p, p->d_b.ptr, lam_ptr(p), p->d_work.ptr + 5, s));
+  return adj_sload(p, v);
+}
+
+// Forward and J^T v for a v given up front (not derived from this forward's
+// D): the adjoint coarse problem A_k lambda_j = S_k^T Rx v_j needs only A_k,
+// S_k and v, so its right-hand sides are gathered beside the forward's and
+// both sets are solved in one launch of 2 Ns columns (t, then lambda).  Each
+// column's iteration is the same as in separate solves, so the results are
+// the same bit for bit.
+msfv_status fwd_adj_coarse(msfv_problem* p, const double* v, double* d_out) {
+  hipStream_t s = p->stream;
+  const int ns = p->src.count;
+  const size_t nc = size_t(p->plan.ncoarse);
+  msfv_status st = coarse_prep(p, 2 * ns);
+  if (st == MSFV_OK) st = adj_rhs(p, v, p->d_b.ptr + nc * ns);
+  if (st != MSFV_OK) return st;
+  STAGE(MSFV_STAGE_COARSE_FWD,
+        coarse_solve(p, p->d_b.ptr, p->d_t.ptr, p->d_work.ptr + 4, s, 2 * ns));
+  st = fwd_data(p, d_out, nullptr);
+  if (st == MSFV_OK) st = adj_sload(p, v);
+  return st;
 }
 
 msfv_status adj_local(msfv_problem* p) {
@@ -787,10 +851,10 @@ msfv_status jtv_fixed_impl(msfv_problem* p, const double* v, double* g_out) {
   HIP_OK(msfv::launch_gather_slots(p->d_rec_dst.ptr, p->d_rec_ptr.ptr, p->d_rec_pidx.ptr, p->d_rec_w.ptr,
                                    p->d_rec_col.ptr, v, nr, p->d_pval.ptr, p->d_b.ptr, p->nrec_slot, ns,
                                    nc, s));
-  HIP_OK(coarse_solve(p, p->d_b.ptr, p->d_lam.ptr, nullptr, s));
+  HIP_OK(coarse_solve(p, p->d_b.ptr, lam_ptr(p), nullptr, s));
   HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_t.ptr, P.ncv, ns, P.ncell,
                               p->d_fu.ptr, p->d_b.ptr, s));
-  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, p->d_lam.ptr, P.ncv, ns, P.ncell,
+  HIP_OK(msfv::launch_prolong(p->d_prow.ptr, p->d_pcol.ptr, p->d_pval.ptr, lam_ptr(p), P.ncv, ns, P.ncell,
                               p->d_fz.ptr, p->d_b.ptr, s));
   HIP_OK(msfv::launch_wfixed(p->g, P.ncell, ns, p->d_fu.ptr, p->d_fz.ptr, p->d_W.ptr, s));
   HIP_OK(msfv::launch_gfinal(p->d_sig.ptr, p->d_W.ptr, p->g, P.ncell, g_out, s));
@@ -831,6 +895,22 @@ msfv_status scratch_address(double** out) {
 // model (eq. senssimple).
 msfv_status jtv_model(msfv_problem* p, const double* v, double* g_out) {
   return p->frozen ? jtv_fixed_impl(p, v, g_out) : jtv_impl(p, v, g_out);
+}
+
+// Forward + J^T v with v given: one coarse launch for both sets of columns
+// (a frozen basis takes its own J^T v, after the forward).
+msfv_status forward_jtv_impl(msfv_problem* p, const double* m, const double* v, double* d_out,
+                             double* g_out) {
+  if (p->frozen) {
+    msfv_status st = forward_impl(p, m, d_out, nullptr);
+    return st == MSFV_OK ? jtv_fixed_impl(p, v, g_out) : st;
+  }
+  msfv_status st = fwd_begin(p, m);
+  if (st == MSFV_OK) st = fwd_local(p);
+  if (st == MSFV_OK) st = fwd_adj_coarse(p, v, d_out);
+  if (st == MSFV_OK) st = adj_local(p);
+  if (st == MSFV_OK) st = adj_end(p, g_out);
+  return st;
 }
 
 msfv_status jvp_model(msfv_problem* p, const double* dm, double* dd_out) {
@@ -1055,6 +1135,12 @@ msfv_status msfv_forward(msfv_problem* p, const double* m, double* d_out, double
 msfv_status msfv_jtv(msfv_problem* p, const double* v, double* g_out) {
   if (!p || !v || !g_out) return fail(MSFV_EINVAL, "null argument");
   return jtv_model(p, v, g_out);
+}
+
+msfv_status msfv_forward_jtv(msfv_problem* p, const double* m, const double* v, double* d_out,
+                             double* g_out) {
+  if (!p || !m || !v || !d_out || !g_out) return fail(MSFV_EINVAL, "null argument");
+  return forward_jtv_impl(p, m, v, d_out, g_out);
 }
 
 msfv_status msfv_jvp(msfv_problem* p, const double* dm, double* dd_out) {
@@ -1352,8 +1438,7 @@ msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, do
   msfv_status st = MSFV_OK;
   // the large coarse solver polls from the host, which a graph cannot hold
   if (!b->graphs || coarse_multi(p)) {
-    st = forward_impl(p, m, d, nullptr);
-    if (st == MSFV_OK) st = jtv_model(p, v, g);
+    st = forward_jtv_impl(p, m, v, d, g);
   } else {
     msfv_batch::Graph& c = b->cache[i];
     if (!c.exec || c.m != m || c.v != v || c.d != d || c.g != g || c.generation != p->generation) {
@@ -1362,8 +1447,7 @@ msfv_status batch_one(msfv_batch* b, int i, const double* m, const double* v, do
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        st = forward_impl(p, m, d, nullptr);
-        if (st == MSFV_OK) st = jtv_model(p, v, g);
+        st = forward_jtv_impl(p, m, v, d, g);
         e = hipStreamEndCapture(s, &graph);
         if (st == MSFV_OK && e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1536,10 +1620,7 @@ msfv_status pipeline_run(msfv_batch* b, msfv_batch::Pipeline* pl, const double* 
     if (!g->adj)
       HIP_OK(g->stage == 1 ? msfv::launch_edge_multi(g->caps, false, pl->main)
                            : msfv::launch_local_multi(g->caps, g->klass, false, pl->main));
-  st = issue_each(b, pl, [&](msfv_problem* p, int i) {
-    msfv_status r = fwd_end(p, d_out[i], nullptr);
-    return r == MSFV_OK ? adj_begin(p, v[i]) : r;
-  });
+  st = issue_each(b, pl, [&](msfv_problem* p, int i) { return fwd_adj_coarse(p, v[i], d_out[i]); });
   if (st != MSFV_OK) return st;
   for (auto& g : pl->groups)
     if (g->adj)
@@ -1877,19 +1958,18 @@ long long request_bytes(const msfv_problem* p, int ns) {
 msfv_status reserve_sources(msfv_problem* p, int max_ns) {
   const size_t ncs = size_t(p->plan.ncoarse) * max_ns;
   const size_t nd = size_t(std::max(1, p->rec.count)) * max_ns;
-  HIP_OK(p->d_b.alloc(size_t(p->plan.ncoarse) * msfv::prolong_ldt(max_ns)));
-  HIP_OK(p->d_t.alloc(ncs));
-  HIP_OK(p->d_lam.alloc(ncs));
+  HIP_OK(p->d_b.alloc(std::max(size_t(p->plan.ncoarse) * msfv::prolong_ldt(max_ns), 2 * ncs)));
+  HIP_OK(p->d_t.alloc(2 * ncs));
   HIP_OK(p->d_D.alloc(nd));
   HIP_OK(p->d_v.alloc(nd));
   if (coarse_multi(p)) {
-    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, max_ns) / sizeof(double) + 1));
-    if (p->flags_cap < max_ns) {
+    HIP_OK(p->d_cg_ws.alloc(msfv::coarse_large_workspace(p->plan.ncv, 2 * max_ns) / sizeof(double) + 1));
+    if (p->flags_cap < 2 * max_ns) {
       if (p->h_flags) HIP_OK(hipHostFree(p->h_flags));
       p->h_flags = nullptr;
       p->flags_cap = 0;
-      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * max_ns));
-      p->flags_cap = max_ns;
+      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), sizeof(int) * 6 * 2 * max_ns));
+      p->flags_cap = 2 * max_ns;
     }
   }
   return MSFV_OK;
@@ -1908,8 +1988,7 @@ msfv_status serve_run(msfv_problem* p, msfv_server::Req& r, hipEvent_t epoch) {
   if (st != MSFV_OK) return st;
   HIP_OK(hipStreamWaitEvent(p->stream, r.ev_ready, 0));  // inputs written on the caller's stream
   HIP_OK(hipEventRecord(r.ev_start, p->stream));
-  st = forward_impl(p, r.m, r.d, nullptr);
-  if (st == MSFV_OK) st = jtv_model(p, r.v, r.g);
+  st = forward_jtv_impl(p, r.m, r.v, r.d, r.g);
   if (st != MSFV_OK) return st;
   HIP_OK(hipEventRecord(r.ev_end, p->stream));
   HIP_OK(hipEventSynchronize(r.ev_end));

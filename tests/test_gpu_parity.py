@@ -208,6 +208,46 @@ def test_coarse_preconditioners_parity(n, r, ns):
     assert out["twolevel"][3] < out["jacobi"][3]
 
 
+@pytest.mark.parametrize("n,r,mode,precond", [
+    ((13, 11, 9), (4, 4, 4), "reduced", "twolevel"),
+    ((17, 9, 12), (8, 3, 4), "lagrange", "jacobi"),
+    ((13, 11, 9), (4, 4, 4), "reduced", "multi"),
+    ((23, 17), (5, 6), "reduced", "twolevel"),
+])
+def test_forward_jtv_joint_coarse_solve(n, r, mode, precond):
+    """msfv_forward_jtv (forward and adjoint coarse problems in one launch of
+    2 Ns columns) gives D and J^T v bit for bit equal to msfv_forward then
+    msfv_jtv, and D, t and g agree with the oracle; with a frozen basis it
+    takes the fixed-basis J^T v."""
+    torch = _torch()
+    inst = W.small_instance(n, r, seed=18, ns=3, nr=5)
+    prob = _problem(n, r, mode, inst, coarse_precond=precond)
+    m = torch.tensor(inst.m, dtype=torch.float64, device="cuda")
+    V = np.random.default_rng(19).standard_normal((inst.receivers.count, inst.sources.count))
+    v = torch.tensor(V.T.copy(), device="cuda")
+    D1 = prob.forward(m).clone()
+    g1 = prob.jtv(v).clone()
+    D2, g2 = prob.forward_jtv(m, v)
+    assert torch.equal(D1, D2) and torch.equal(g1, g2)
+    s = prob.stats()
+    assert s.local_noconv == 0 and s.coarse_noconv == 0
+    geo = Geometry(n, r)
+    st = R.forward(geo, inst.m, inst.sources, inst.receivers, mode=mode)
+    _, t = prob.coarse()
+    PT.rows(t, st.t.T, 1e-10, "t")
+    PT.rows(D2.cpu().numpy(), st.D.T, 1e-10, "D")
+    PT.vector(g2.cpu().numpy(), R.jtv(st, V), 1e-8, "g")
+    # frozen basis: forward with the frozen rows, then the fixed-basis J^T v
+    prob.freeze_basis(True)
+    m2 = m + 0.05 * torch.tensor(np.random.default_rng(20).standard_normal(m.shape[0]), device="cuda")
+    D3 = prob.forward(m2).clone()
+    g3 = prob.jtv(v).clone()
+    D4, g4 = prob.forward_jtv(m2, v)
+    assert torch.equal(D3, D4) and torch.equal(g3, g4)
+    prob.freeze_basis(False)
+    prob.close()
+
+
 def test_determinism_and_stats():
     torch = _torch()
     n, r = (13, 11, 9), (4, 4, 4)
