@@ -47,6 +47,7 @@ STAGE_WORK = {
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed_r8.json")
+SERVE_HBM_BUDGET = 200e9  # admission budget of the serving workload (bytes)
 
 
 def measured_traffic(kernel_stage: str):
@@ -331,7 +332,7 @@ def run_serve(jobs: int, nreq: int, inflight: int, log=sys.stderr) -> dict:
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
     js = W.workload_serving(jobs)
-    srv = msfv.Server(max_inflight=inflight)
+    srv = msfv.Server(max_inflight=inflight, hbm_budget=SERVE_HBM_BUDGET)
     state = []
     rng = np.random.default_rng(W.config_seed(5, 999))
     for k, job in enumerate(js):
@@ -395,6 +396,7 @@ def run_serve(jobs: int, nreq: int, inflight: int, log=sys.stderr) -> dict:
     for s in state:
         s["p"].close()
     return {"jobs": len(js), "requests_per_point": nreq, "max_inflight": inflight,
+            "hbm_budget_bytes": SERVE_HBM_BUDGET,
             "capacity_per_s": cap, "closed_loop_p50_ms": closed["p50_ms"],
             "closed_loop_p99_ms": closed["p99_ms"], "load_points": points, "setup_s": setup_s,
             "job_sizes": [j.n[0] for j in js]}

@@ -1192,6 +1192,9 @@ __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int la
   cum[0] = 0.0;
   for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
   double M[4] = {0, 0, 0, 0};
+  // unrolled: the loads of several sources in flight together (the sums
+  // keep their order)
+#pragma unroll 8
   for (int j = 0; j < a.ns; ++j) {
     const double t0 = a.t[size_t(j) * a.ncoarse + E.vid[0]], t1 = a.t[size_t(j) * a.ncoarse + E.vid[1]];
     const double l0 = a.lam[size_t(j) * a.ncoarse + E.vid[0]], l1 = a.lam[size_t(j) * a.ncoarse + E.vid[1]];
@@ -1338,10 +1341,21 @@ __global__ void k_gather_slots(const int* slot_dst, const int* slot_ptr, const i
   if (t >= (long long)nslot * ncol) return;
   const int s = int(t % nslot), j = int(t / nslot);
   double acc = 0.0;
-  for (int e = slot_ptr[s]; e < slot_ptr[s + 1]; ++e) {
-    double w = ent_w[e] * pval[ent_pidx[e]];
-    if (colw) w *= colw[size_t(j) * colw_ld + ent_col[e]];
-    acc += w;
+  const int e0 = slot_ptr[s], e1 = slot_ptr[s + 1];
+  // the slot's entries four at a time, their loads in flight together
+  for (int eb = e0; eb < e1; eb += 4) {
+    double w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = eb + u;
+      w[u] = 0.0;
+      if (e >= e1) continue;
+      w[u] = ent_w[e] * pval[ent_pidx[e]];
+      if (colw) w[u] *= colw[size_t(j) * colw_ld + ent_col[e]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (eb + u < e1) acc += w[u];
   }
   out[slot_dst[s] + size_t(j) * nc] = acc;
 }
@@ -1503,10 +1517,14 @@ __global__ void k_sload(int nelec, const int* ecell, const int* rptr, const int*
   double acc = 0.0;
   if (c < len) {
     const int vid = pcol[a + c];
-    for (int j = 0; j < ns; ++j) {
-      double w = 0.0;
-      for (int q = rptr[e]; q < rptr[e + 1]; ++q) w += rw[q] * v[size_t(j) * nr + ridx[q]];
-      acc += t[size_t(j) * nc + vid] * w;
+    const double* tv = t + vid;
+    // receivers at the cell (usually one), then the sources in an unrolled
+    // loop whose loads are in flight together
+    for (int q = rptr[e]; q < rptr[e + 1]; ++q) {
+      const double wq = rw[q];
+      const double* vq = v + ridx[q];
+#pragma unroll 8
+      for (int j = 0; j < ns; ++j) acc += tv[size_t(j) * nc] * (wq * vq[size_t(j) * nr]);
     }
     for (int q = sptr[e]; q < sptr[e + 1]; ++q) acc += lam[size_t(sidx[q]) * nc + vid] * sw[q];
   }
@@ -1514,10 +1532,7 @@ __global__ void k_sload(int nelec, const int* ecell, const int* rptr, const int*
 }
 
 // g_i = sum over the fluxes f of cell i of dT_f/dm_i W_f, with sigma = exp(m)
-// precomputed: workgroups walk x-rows of cells (xb workgroups a row), so a
-// cell's coordinates come from the workgroup's row without a per-cell
-// division.
-// One workgroup a span of 256 consecutive cells.  Workgroups go round-robin
+// precomputed.  One workgroup a span of 256 consecutive cells.  Workgroups go round-robin
 // over the eight XCDs (workgroup L to XCD L mod 8), so span = (L mod 8) * spx
 // + L / 8 gives XCD x the contiguous spans [x spx, (x+1) spx): the rows and
 // planes whose sigma and W a span reads around its own cells (i +- n_x,
@@ -1631,10 +1646,23 @@ __global__ void k_residual(const double* D, const double* dobs, double* v, long 
                            double* phi) {
   __shared__ double red[16 * 4];
   double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
-    const double r = D[i] - dobs[i];
-    v[i] = r;
-    s += r * r;
+  // eight elements a thread per pass, their loads in flight together
+  for (long long i0 = threadIdx.x; i0 < n; i0 += 8LL * blockDim.x) {
+    double d[8], o[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long i = i0 + u * (long long)blockDim.x;
+      d[u] = i < n ? D[i] : 0.0;
+      o[u] = i < n ? dobs[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long i = i0 + u * (long long)blockDim.x;
+      if (i >= n) continue;
+      const double r = d[u] - o[u];
+      v[i] = r;
+      s += r * r;
+    }
   }
   double arr[1] = {s};
   block_sum<16, 1>(arr, 1, red);
