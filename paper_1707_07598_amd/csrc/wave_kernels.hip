@@ -734,21 +734,28 @@ __device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* p
     const int t = i / E.cext[0];
     const int ly = t % E.cext[1];
     const int lz = t / E.cext[1];
-    if (skip_own) {
-      const int ox = E.clo[0] + lx - E.ulo[0], oy = E.clo[1] + ly - E.ulo[1], oz = E.clo[2] + lz - E.ulo[2];
-      if (ox >= 0 && ox < E.uext[0] && oy >= 0 && oy < E.uext[1] && oz >= 0 && oz < E.uext[2]) continue;
-    }
+    const int ox = E.clo[0] + lx - E.ulo[0], oy = E.clo[1] + ly - E.ulo[1], oz = E.clo[2] + lz - E.ulo[2];
+    const bool own = ox >= 0 && ox < E.uext[0] && oy >= 0 && oy < E.uext[1] && oz >= 0 && oz < E.uext[2];
+    if (skip_own && own) continue;
     const int gid = (E.clo[0] + lx) + a.g.s1 * (E.clo[1] + ly) + a.g.s2 * (E.clo[2] + lz);
     const int r0 = a.prow[gid], r1 = a.prow[gid + 1];
     double v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = 0.0;
-    for (int e = r0; e < r1; ++e) {
-      const int vid = a.pcol[e];
-      const double val = pv[e];
+    if (own) {
+      // an own cell's row holds exactly the entity's corners, in corner
+      // order: no column matching, all loads at once
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < nc && E.vid[q] == vid) v[q] = val;
+        if (q < nc) v[q] = pv[r0 + q];
+    } else {
+      for (int e = r0; e < r1; ++e) {
+        const int vid = a.pcol[e];
+        const double val = pv[e];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nc && E.vid[q] == vid) v[q] = val;
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
