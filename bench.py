@@ -11,6 +11,14 @@ Galerkin coarse operator, the coarse solves for all 32 sources, the data,
 the residual against observed data, and J_k^T of that residual through the
 change of basis (one "solve" in solves/s).  Inputs are resident in HBM before
 the timed region.  Prints one JSON line.
+
+Besides the headline, the line carries (unless --no-extra) compact figures
+of the other workloads measured in the same run: forward only at 64^3 (r 8,
+16 dipoles, 256 receivers), the 64-instance mixed batch through the batch
+entry points against the same instances one after another, and the serving
+loop (16 jobs, Poisson arrivals at 0.5x, 1x and 2x its measured capacity,
+200 GB admission budget).  --workload batch / serve print the full lines of
+those workloads instead.
 """
 from __future__ import annotations
 
@@ -151,6 +159,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload only: skip the forward-only 64^3, batch and serving figures "
+                         "appended to its line")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-stage events")
     ap.add_argument("--workload", choices=["c3", "batch", "serve"], default="c3",
@@ -311,6 +322,18 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)
     prob.close()
+    if not args.no_extra:
+        # the other workloads, compact: forward only at 64^3, the 64-instance
+        # batch (autotuned form against one instance after another) and the
+        # serving loop (capacity, latency percentiles at 0.5x, 1x, 2x load)
+        torch.cuda.synchronize()
+        out["forward_only_64"] = forward_only_64()
+        out["batch"] = measure_batch(8, 1, args.batch_count, sweep=False)
+        sv = run_serve(args.serve_jobs, args.serve_requests, args.serve_inflight)
+        out["serve"] = {"jobs": sv["jobs"], "requests_per_point": sv["requests_per_point"],
+                        "hbm_budget_bytes": sv["hbm_budget_bytes"], "capacity_per_s": sv["capacity_per_s"],
+                        "load_points": {k: {kk: v[kk] for kk in ("served_per_s", "p50_ms", "p99_ms", "failed")}
+                                        for k, v in sv["load_points"].items()}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -402,12 +425,13 @@ def run_serve(jobs: int, nreq: int, inflight: int, log=sys.stderr) -> dict:
             "job_sizes": [j.n[0] for j in js]}
 
 
-def run_batch(args) -> int:
+def measure_batch(steps: int, warmup: int, count: int, sweep: bool = True) -> dict:
     """Mixed batch: cubic n ~ U{48..160} (n mod r != 0), r ~ U{4, 8, 16},
     Ns ~ U{1..32} dipoles, 16 x 16 receivers; one solve = forward + J^T v of
     one instance.  The plain form runs the instances one after another on
     one stream; the batch form issues them through msfv_batch_* with the
-    autotuned stream count and graphs."""
+    autotuned options.  With ``sweep`` each form is also timed at its best
+    stream count."""
     import numpy as np
     import torch
 
@@ -417,7 +441,7 @@ def run_batch(args) -> int:
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    insts = W.workload_batch(args.batch_count)
+    insts = W.workload_batch(count)
     probs, ms, vs = [], [], []
     for k, inst in enumerate(insts):
         p = msfv.Problem(inst.n, inst.r, "reduced")
@@ -439,7 +463,7 @@ def run_batch(args) -> int:
         p.forward(m, sync=False)
         p.jtv(v, sync=False)
     torch.cuda.synchronize()
-    reps = max(1, args.steps // 10)
+    reps = max(1, steps // 10)
     t0 = time.perf_counter()
     for _ in range(reps):
         for p, m, v in zip(probs, ms, vs):
@@ -452,13 +476,13 @@ def run_batch(args) -> int:
 
     b = msfv.Batch(probs)
 
-    def timed(steps):
-        for _ in range(args.warmup):
+    def timed(nsteps):
+        for _ in range(warmup):
             b.forward_jtv(ms, vs, sync=False)
         b.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(nsteps):
             b.forward_jtv(ms, vs, sync=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -469,38 +493,80 @@ def run_batch(args) -> int:
     # each form at its best stream count: the per-problem path (graphs) and
     # the shared launches of the local solves across problems
     forms = {}
-    for name, graphs, shared in (("streams+graphs", True, 0), ("shared launches, 1 pipeline", False, 1),
-                                 ("shared launches, 2 pipelines", False, 2),
-                                 ("shared launches, 4 pipelines", False, 4)):
-        best = None
-        for sc in (4, 8, 16):
-            if sc < 2 * shared:
-                continue
-            b.set_options(sc, graphs, shared)
-            dt = timed(max(1, args.steps // 4))
-            if best is None or dt < best[0]:
-                best = (dt, sc)
-        forms[name] = {"streams": best[1], "solves_per_s": n * max(1, args.steps // 4) / best[0]}
+    if sweep:
+        for name, graphs, shared in (("streams+graphs", True, 0), ("shared launches, 1 pipeline", False, 1),
+                                     ("shared launches, 2 pipelines", False, 2),
+                                     ("shared launches, 4 pipelines", False, 4)):
+            best = None
+            for sc in (4, 8, 16):
+                if sc < 2 * shared:
+                    continue
+                b.set_options(sc, graphs, shared)
+                dt = timed(max(1, steps // 4))
+                if best is None or dt < best[0]:
+                    best = (dt, sc)
+            forms[name] = {"streams": best[1], "solves_per_s": n * max(1, steps // 4) / best[0]}
     streams, graphs, shared = b.autotune(ms, vs)
-    elapsed = timed(args.steps)
-    value = n * args.steps / elapsed
+    elapsed = timed(steps)
+    value = n * steps / elapsed
     out = {
-        "metric": "MSFV forward+J^T v solves/s, batch of mixed instances (one solve = one instance)",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batch-{n}-mixed-n48..160-r4/8/16-ns1..32", "instances": n,
-                   "fine_cells": cells, "sources": int(sum(i.sources.count for i in insts)),
-                   "bc_mode": "reduced"},
+        "solves_per_s": value, "steps": steps, "ms_per_step": 1e3 * elapsed / steps,
+        "workload": f"batch-{n}-mixed-n48..160-r4/8/16-ns1..32", "instances": n,
+        "fine_cells": cells, "sources": int(sum(i.sources.count for i in insts)),
         "plain_solves_per_s": n / plain_s, "speedup_vs_plain": value / (n / plain_s),
-        "forms": forms,
         "autotuned": {"streams": streams, "graphs": graphs, "shared": shared}, "setup_s": setup_s,
     }
+    if sweep:
+        out["forms"] = forms
     b.close()
     for p in probs:
         p.close()
+    return out
+
+
+def run_batch(args) -> int:
+    bt = measure_batch(args.steps, args.warmup, args.batch_count, sweep=True)
+    out = {
+        "metric": "MSFV forward+J^T v solves/s, batch of mixed instances (one solve = one instance)",
+        "value": bt["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": bt["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": bt["workload"], "instances": bt["instances"], "fine_cells": bt["fine_cells"],
+                   "sources": bt["sources"], "bc_mode": "reduced"},
+        "plain_solves_per_s": bt["plain_solves_per_s"], "speedup_vs_plain": bt["speedup_vs_plain"],
+        "forms": bt["forms"], "autotuned": bt["autotuned"], "setup_s": bt["setup_s"],
+    }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def forward_only_64(steps: int = 10) -> dict:
+    """The 64^3 workload (r = 8, 16 dipoles, 256 receivers, two box
+    anomalies): forward only, one instance per call."""
+    import torch
+
+    import paper_1707_07598_amd as msfv
+    import workloads as W
+
+    inst = W.workload_64()
+    dev = torch.device("cuda", 0)
+    prob = msfv.Problem(inst.n, inst.r, "reduced")
+    prob.set_sources(inst.sources)
+    prob.set_receivers(inst.receivers)
+    m = torch.tensor(inst.m, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        prob.forward(m, sync=False)
+    prob.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.forward(m, sync=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prob.sync()
+    prob.close()
+    return {"workload": "3d-64^3-r8-16dipoles-256rx-forward", "forward_solves_per_s": steps / dt,
+            "ms_per_forward": 1e3 * dt / steps}
 
 
 if __name__ == "__main__":
