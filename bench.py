@@ -496,7 +496,8 @@ def measure_batch(steps: int, warmup: int, count: int, sweep: bool = True) -> di
     if sweep:
         for name, graphs, shared in (("streams+graphs", True, 0), ("shared launches, 1 pipeline", False, 1),
                                      ("shared launches, 2 pipelines", False, 2),
-                                     ("shared launches, 4 pipelines", False, 4)):
+                                     ("shared launches, 4 pipelines", False, 4),
+                                     ("shared launches, 8 pipelines", False, 8)):
             best = None
             for sc in (4, 8, 16):
                 if sc < 2 * shared:

@@ -313,7 +313,7 @@ const char* msfv_stage_name(int stage);
  *                     per-problem path.  set_options waits for the batch's
  *                     work.
  * msfv_batch_autotune : times one call per candidate (shared launches in 1,
- *                     2 or 4 pipelines, or the per-problem path with and
+ *                     2, 4 or 8 pipelines, or the per-problem path with and
  *                     without graphs; streams 1, 2, 4, 8, 16 capped at
  *                     count) with the given buffers, keeps the fastest and
  *                     reports it. */

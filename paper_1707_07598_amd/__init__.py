@@ -444,7 +444,7 @@ class Batch:
         return s.value, bool(g.value), sh.value
 
     def autotune(self, ms, vs):
-        """Time each candidate (shared launches in 1, 2 or 4 pipelines, or
+        """Time each candidate (shared launches in 1, 2, 4 or 8 pipelines, or
         the per-problem path with or without graphs, times the stream count)
         once and keep the fastest; returns (streams, graphs, shared)."""
         self._check_inputs(ms, vs)

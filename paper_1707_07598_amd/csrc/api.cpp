@@ -1836,14 +1836,15 @@ msfv_status msfv_batch_autotune(msfv_batch* b, const double* const* m, const dou
   double best = 1e300;
   int best_s = b->streams, best_sh = b->shared;
   bool best_g = b->graphs;
-  // candidates: shared launches of the local solves in 1, 2 or 4
+  // candidates: shared launches of the local solves in 1, 2, 4 or 8
   // pipelines, or each problem's whole sequence on the stream pool, replayed
   // from HIP graphs or issued eagerly; each over 1..16 streams
   struct Cand {
     int shared;
     bool graphs;
   };
-  for (const Cand c : {Cand{1, false}, Cand{2, false}, Cand{4, false}, Cand{0, true}, Cand{0, false}}) {
+  for (const Cand c : {Cand{1, false}, Cand{2, false}, Cand{4, false}, Cand{8, false}, Cand{0, true},
+                       Cand{0, false}}) {
     if (c.shared > count) continue;
     for (int sc : {1, 2, 4, 8, 16}) {
       if (sc > count && sc != 1) continue;
