@@ -424,8 +424,9 @@ __device__ double coons_value(const EntDesc& E, const GridInfo& g, const int* pr
 }
 
 template <int BLOCK, int CPT>
-__device__ void load_closure_sigma(const EntDesc& E, const GridInfo& g, const double* m,
+__device__ void load_closure_sigma(const EntDesc& E, const GridInfo& g, const double* sigma,
                                    double* sig) {
+  // sigma = exp(m) of the call's model, formed once per cell by the model copy
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   for (int i = threadIdx.x; i < ncl; i += BLOCK) {
     const int lx = i % E.cext[0];
@@ -433,7 +434,7 @@ __device__ void load_closure_sigma(const EntDesc& E, const GridInfo& g, const do
     const int ly = t % E.cext[1];
     const int lz = t / E.cext[1];
     const int gid = (E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz);
-    sig[i] = exp(m[gid]);
+    sig[i] = sigma[gid];
   }
 }
 
@@ -449,7 +450,7 @@ __device__ __forceinline__ void local_fwd_body(const LocalParams& a, int eid, do
   double* redA = pb + NCP * a.nu_cap;
   double* redB = redA + NW * 40;
   double* tp = redB + NW * 40;  // 3 * nu_cap
-  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.sig, sig);
   __syncthreads();
   CellGeo cg[CPT];
 #pragma unroll
@@ -632,7 +633,7 @@ __device__ __forceinline__ void local_tan_body(const LocalParams& a, int eid, do
   double* redA = pb + NCP * a.nu_cap;
   double* redB = redA + NW * 40;
   double* tp = redB + NW * 40;  // 3 * nu_cap
-  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.sig, sig);
   __syncthreads();
   CellGeo cg[CPT];
 #pragma unroll
@@ -786,7 +787,7 @@ __device__ __forceinline__ void local_adj_body(const LocalParams& a, int eid, do
   double* Mm = redB + NW * 40;  // 64
   double* Sm = Mm + 64;         // 64
   double* tp = Sm + 64;         // 3 * nu_cap
-  load_closure_sigma<BLOCK, CPT>(E, a.g, a.m, sig);
+  load_closure_sigma<BLOCK, CPT>(E, a.g, a.sig, sig);
   const int nc = E.nc;
   if (threadIdx.x < nc * nc) {
     const int c = threadIdx.x / nc, c2 = threadIdx.x % nc;
@@ -1048,13 +1049,14 @@ struct EdgeLine {
   double T[kMaxLine];
 };
 
-__device__ void edge_line(const EntDesc& E, const GridInfo& g, const double* m, EdgeLine& L) {
+// sigma = exp(m) of the call's model (formed once per cell by the model copy)
+__device__ void edge_line(const EntDesc& E, const GridInfo& g, const double* sigma, EdgeLine& L) {
   L.k = (E.open_mask & 1) ? 0 : ((E.open_mask & 2) ? 1 : 2);
   L.len = E.cext[L.k];
   L.base = E.clo[0] + g.s1 * E.clo[1] + g.s2 * E.clo[2];
   L.st = gstride_of(g, L.k);
   L.u0 = E.ulo[L.k] - E.clo[L.k];
-  for (int i = 0; i < L.len; ++i) L.sig[i] = exp(m[L.base + i * L.st]);
+  for (int i = 0; i < L.len; ++i) L.sig[i] = sigma[L.base + i * L.st];
   for (int i = 0; i + 1 < L.len; ++i) L.T[i] = harm(L.sig[i], L.sig[i + 1]);
 }
 
@@ -1079,7 +1081,7 @@ __device__ __forceinline__ void edge_phi(const EntDesc& E, const EdgeLine& L, co
 __device__ __forceinline__ void edge_fwd_one(const LocalParams& a, int e, int lagrange) {
   const EntDesc E = a.ents[e];
   EdgeLine L;
-  edge_line(E, a.g, a.m, L);
+  edge_line(E, a.g, a.sig, L);
   double cum[kMaxLine];
   cum[0] = 0.0;
   for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
@@ -1128,7 +1130,7 @@ __global__ void k_edge_tan(LocalParams a, int lagrange) {
   if (e >= a.nent) return;
   const EntDesc E = a.ents[e];
   EdgeLine L;
-  edge_line(E, a.g, a.m, L);
+  edge_line(E, a.g, a.sig, L);
   double cum[kMaxLine], dcum[kMaxLine], dT[kMaxLine];
   cum[0] = dcum[0] = 0.0;
   for (int i = 0; i + 1 < L.len; ++i) {
@@ -1181,7 +1183,7 @@ __global__ void k_edge_tan(LocalParams a, int lagrange) {
 __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int lagrange) {
   const EntDesc E = a.ents[e];
   EdgeLine L;
-  edge_line(E, a.g, a.m, L);
+  edge_line(E, a.g, a.sig, L);
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   double* Wk = a.W + L.k * N;
   if (E.nc == 1) {  // strip: s = 1 for every m, nothing depends on m

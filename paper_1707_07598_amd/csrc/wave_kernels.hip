@@ -294,15 +294,16 @@ __device__ __forceinline__ void own_coords(const EntDesc& E, const WGeo& w, int 
 
 // sigma on the closure, sqrt of the operator diagonal, scaled transmissibilities
 template <int BLOCK>
-__device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* __restrict__ m,
+__device__ void shared_setup(const EntDesc& E, const GridInfo& g, const double* __restrict__ sigma,
                              double* sig, double* dsq, double* tt, const WGeo& w, bool op = true) {
+  // sigma = exp(m) of the call's model, formed once per cell by the model copy
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   for (int i = threadIdx.x; i < ncl; i += BLOCK) {
     const int lx = i % E.cext[0];
     const int t = i / E.cext[0];
     const int ly = t % E.cext[1];
     const int lz = t / E.cext[1];
-    sig[i] = exp(m[(E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz)]);
+    sig[i] = sigma[(E.clo[0] + lx) + g.s1 * (E.clo[1] + ly) + g.s2 * (E.clo[2] + lz)];
   }
   __syncthreads();
   if (!op) return;  // sigma only: no local solve follows
@@ -790,7 +791,7 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
   load_phi_table<BLOCK>(E, a, S.phi, !a.prescribe);
-  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  shared_setup<BLOCK>(E, a.g, a.sig, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia0 = lane % w.lw, ib0 = lane / w.lw;
@@ -1114,7 +1115,7 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
   // adjoint loads (dual blocks off the electrodes): no local operator, no
   // solve, only the pushes of y_c and the flux weights
   const bool loaded = a.solve_adj && (E.nslot > 0 || E.eptr1 > E.eptr0);
-  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w, loaded);
+  shared_setup<BLOCK>(E, a.g, a.sig, S.sig, S.dsq, S.tt, w, loaded);
   __syncthreads();
   if (threadIdx.x < nc * nc) {
     const int q = threadIdx.x / nc, q2 = threadIdx.x % nc;
@@ -1469,7 +1470,7 @@ __global__ __launch_bounds__(NWAVE * 64) void k_wave_tan(LocalParams a) {
     const int ly = t % E.cext[1], lz = t / E.cext[1];
     dmv[i] = a.dm[(E.clo[0] + lx) + a.g.s1 * (E.clo[1] + ly) + a.g.s2 * (E.clo[2] + lz)];
   }
-  shared_setup<BLOCK>(E, a.g, a.m, S.sig, S.dsq, S.tt, w);
+  shared_setup<BLOCK>(E, a.g, a.sig, S.sig, S.dsq, S.tt, w);
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia0 = lane % w.lw, ib0 = lane / w.lw;
