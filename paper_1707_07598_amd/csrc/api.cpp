@@ -154,8 +154,14 @@ struct msfv_problem {
   // (geometry fixed at compile time) first, then the others
   DevBuf<int> d_blist;
   std::vector<int> h_blist;
-  DevBuf<int> d_flist;  // faces in launch order
   int full_u = 0, nfull = 0, nrest = 0;
+  // faces in launch order: the full faces of face_u x face_u own cells
+  // (nface_full, grouped by plane axis), then the others (nface_rest);
+  // faces_one_launch: the others fit the same wave kernel
+  DevBuf<int> d_flist;
+  std::vector<int> h_flist;
+  int face_u = 0, nface_full = 0, nface_rest = 0;
+  bool faces_one_launch = false;
   // sensitivity passes (allocated on first use)
   DevBuf<double> d_dpval, d_dkent, d_dkval, d_dkdia, d_dt, d_fu, d_fz;
   DevBuf<int> d_ccptr, d_ccidx, d_cccell;  // column lists of S_k
@@ -485,6 +491,37 @@ hipError_t launch_blocks(msfv_problem* p, const msfv::LocalParams& lp, bool adj,
   return hipSuccess;
 }
 
+// Launch caps of the full faces of u x u own cells.
+void face_caps(msfv::LocalParams& lp, int u) {
+  lp.nu_cap = u * u;
+  lp.sig_cap = (u + 2) * (u + 2);
+  lp.lane_cap = u * u;
+  lp.col_cap = 1;
+  lp.nc_cap = 4;
+  lp.plane_cap = msfv::wave_plane(u, u);
+}
+
+// Local solves of the faces: the full faces through bodies specialised for
+// their shape, in one launch with the others where those fit the same wave
+// kernel, else the others through the general kernels.
+hipError_t launch_faces(msfv_problem* p, const msfv::LocalParams& lp, bool adj, hipStream_t s) {
+  if (p->nface_full > 0 && p->faces_one_launch) return msfv::launch_wave_faces(lp, p->face_u, adj, s);
+  if (p->nface_full > 0) {
+    msfv::LocalParams f = lp;
+    face_caps(f, p->face_u);
+    f.nent = p->nface_full;
+    const hipError_t e = msfv::launch_wave_faces(f, p->face_u, adj, s);
+    if (e != hipSuccess) return e;
+  }
+  if (p->nface_rest > 0) {
+    msfv::LocalParams r = lp;
+    r.ent_list = p->d_flist.ptr + p->nface_full;
+    r.nent = p->nface_rest;
+    return adj ? msfv::launch_local_adj(r, 0, s) : msfv::launch_local_fwd(r, 0, s);
+  }
+  return hipSuccess;
+}
+
 msfv_status ensure_ready(msfv_problem* p) {
   if (p->src.count <= 0) return fail(MSFV_ESTATE, "no sources set");
   if (p->rec.count <= 0) return fail(MSFV_ESTATE, "no receivers set");
@@ -573,7 +610,7 @@ msfv_status fwd_local(msfv_problem* p) {
   msfv::LocalParams lp = local_params(p, 1, false);
   STAGE(MSFV_STAGE_EDGE_FWD, msfv::launch_edge_fwd(lp, lagrange ? 1 : 0, s));
   lp = local_params(p, 2, false);
-  STAGE(MSFV_STAGE_FACE_FWD, msfv::launch_local_fwd(lp, 0, s));
+  STAGE(MSFV_STAGE_FACE_FWD, launch_faces(p, lp, false, s));
   if (P.dim == 3) {
     lp = local_params(p, 3, false);
     STAGE(MSFV_STAGE_BLOCK_FWD, launch_blocks(p, lp, false, s));
@@ -706,7 +743,7 @@ msfv_status adj_local(msfv_problem* p) {
     STAGE(MSFV_STAGE_BLOCK_ADJ, launch_blocks(p, lp, true, s));
   }
   lp = local_params(p, 2, true);
-  STAGE(MSFV_STAGE_FACE_ADJ, msfv::launch_local_adj(lp, 0, s));
+  STAGE(MSFV_STAGE_FACE_ADJ, launch_faces(p, lp, true, s));
   lp = local_params(p, 1, true);
   STAGE(MSFV_STAGE_EDGE_ADJ, msfv::launch_edge_adj(lp, lagrange ? 1 : 0, s));
   return MSFV_OK;
@@ -1045,10 +1082,53 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
     p->h_blist = full;
     if (full.empty()) full.push_back(0);
     HIP_OR_CLEAN(p->d_blist.upload(full, s));
-    // the faces, dealt the same way
-    std::vector<int> faces(P.faces.size());
-    for (size_t i = 0; i < faces.size(); ++i) faces[i] = int(i);
-    faces = deal_over_xcds(faces);
+    // full faces (and the full dual blocks of a 2-D grid): U x U own cells
+    // on a plane of axis k, bounded by vertex planes on both open axes (the
+    // test the face kernels make to pick the body for the shape)
+    auto face_of = [](const msfv::EntDesc& E, int* nax) {
+      *nax = -1;
+      if (E.nc != 4 || E.bounded_mask != E.open_mask) return 0;
+      int U = 0;
+      for (int k = 0; k < 3; ++k) {
+        if ((E.open_mask >> k) & 1) {
+          if (U == 0) U = E.uext[k];
+          if (E.uext[k] != U || E.cext[k] != U + 2 || E.clo[k] != E.ulo[k] - 1) return 0;
+        } else {
+          if (*nax >= 0) return 0;
+          *nax = k;
+          if (E.uext[k] != 1 || E.cext[k] != 1 || E.clo[k] != E.ulo[k]) return 0;
+        }
+      }
+      if (*nax < 0 || (U != 3 && U != 7) || E.nu != U * U) return 0;
+      return U;
+    };
+    int fc3 = 0, fc7 = 0, nax = -1;
+    for (const auto& E : P.faces) {
+      const int u = face_of(E, &nax);
+      fc3 += u == 3;
+      fc7 += u == 7;
+    }
+    const int fbest = fc7 >= fc3 ? (fc7 ? 7 : 0) : 3;
+    std::vector<int> by_axis[3], frest;
+    for (int i = 0; i < int(P.faces.size()); ++i) {
+      const int u = face_of(P.faces[i], &nax);
+      (fbest && u == fbest ? by_axis[nax] : frest).push_back(i);
+    }
+    // launch order: the full faces of each plane axis, then the others, each
+    // run dealt over the XCDs (the waves resident at a time mostly take one
+    // body of the kernel)
+    p->face_u = fbest;
+    std::vector<int> faces;
+    for (int k = 0; k < 3; ++k) {
+      const std::vector<int> dealt = deal_over_xcds(by_axis[k]);
+      faces.insert(faces.end(), dealt.begin(), dealt.end());
+    }
+    p->nface_full = int(faces.size());
+    p->nface_rest = int(frest.size());
+    p->faces_one_launch = P.caps_face.lane <= 64 && P.caps_face.col <= 1 && P.caps_face.nc <= 4;
+    const std::vector<int> dealt = deal_over_xcds(frest);
+    faces.insert(faces.end(), dealt.begin(), dealt.end());
+    p->h_flist = faces;
     if (faces.empty()) faces.push_back(0);
     HIP_OR_CLEAN(p->d_flist.upload(faces, s));
   }
@@ -1516,7 +1596,17 @@ msfv_status shared_build(msfv_batch* b, msfv_batch::Pipeline* pl) {
       msfv_status st = add(local_params(p, 1, adj), 1, adj, 0, nullptr, int(P.edges.size()));
       if (st != MSFV_OK) return st;
       msfv::LocalParams lf = local_params(p, 2, adj);
-      st = add(lf, 2, adj, msfv::local_class(lf), nullptr, int(P.faces.size()));
+      if (p->nface_full > 0 && p->faces_one_launch) {
+        st = add(lf, 2, adj, msfv::faces_class(p->face_u), p->h_flist.data(), p->nface_full + p->nface_rest);
+      } else {
+        if (p->nface_full > 0) {
+          msfv::LocalParams lff = lf;
+          face_caps(lff, p->face_u);
+          st = add(lff, 2, adj, msfv::faces_class(p->face_u), p->h_flist.data(), p->nface_full);
+        }
+        if (st == MSFV_OK)
+          st = add(lf, 2, adj, msfv::local_class(lf), p->h_flist.data() + p->nface_full, p->nface_rest);
+      }
       if (st != MSFV_OK) return st;
       if (P.dim == 3) {
         msfv::LocalParams lb = local_params(p, 3, adj);

@@ -1774,6 +1774,8 @@ int local_class(const LocalParams& p) {
 
 int full_class(int u) { return u == 7 ? kClassFull7 : (u == 3 ? kClassFull3 : kClassNone); }
 
+int faces_class(int u) { return u == 7 ? kClassFaces7 : (u == 3 ? kClassFaces3 : kClassNone); }
+
 int local_class_uni_cap(const LocalParams& p, int klass) {
   return klass < kClassLocalFirst ? wave_class_uni_cap(p, klass) : 0;
 }

@@ -153,18 +153,20 @@ hipError_t launch_coarse_pcg(const double* kdia, const int ncv[3], const double*
 // frozen basis (wave_kernels.hip)
 hipError_t launch_energy_frozen(const LocalParams& p, hipStream_t s);
 // Multi-instance local solves.  A class is the kernel variant that
-// launch_local_* (or launch_wave_full, for the full blocks) would pick for a
-// problem's entity list; items of one class from many problems run in one
-// launch of a fixed grid.  p carries multi, items, nent and the largest caps
+// launch_local_* (or launch_wave_full / launch_wave_faces, for the full
+// blocks and faces) would pick for a problem's entity list; items of one
+// class from many problems run in one launch of a fixed grid.  p carries multi, items, nent and the largest caps
 // over the problems of the class (for the LDS size).
 enum LocalClass {
   kClassNone = 0,
   kClassWave441 = 1, kClassWave443, kClassWave447, kClassWave481, kClassWave483, kClassWave487,
   kClassFull3, kClassFull7,
+  kClassFaces3, kClassFaces7,  // faces, the full 3 x 3 (7 x 7) ones with their shape fixed
   kClassLocalFirst = 16  // + index of the generic variant
 };
 int local_class(const LocalParams& p);      // class of a problem's launch (caps of p)
 int full_class(int u);                      // class of full u^3 blocks
+int faces_class(int u);                     // class of faces whose full ones have u x u own cells
 // uni_cap a problem's parameters must carry in a launch of class klass
 int local_class_uni_cap(const LocalParams& p, int klass);
 hipError_t launch_local_multi(const LocalParams& p, int klass, bool adj, hipStream_t s);
@@ -179,6 +181,11 @@ hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);
 // the same for full dual blocks of u^3 own cells (u = 3 or 7) listed in
 // p.ent_list, with their geometry fixed at compile time
 hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s);
+// and for faces (one cell a lane, caps within one wavefront): the full faces
+// of u x u own cells (u = 3 or 7, bounded by vertex planes on both open
+// axes) through bodies with their geometry fixed, one for each plane axis,
+// the others through the general body, all in one launch
+hipError_t launch_wave_faces(const LocalParams& p, int u, bool adj, hipStream_t s);
 // out[slot_dst[s] + j*nc] = sum_e w[e] * pval[pidx[e]] * (colw ? colw[j*colw_ld + col[e]] : 1)
 // for slot s and column j < ncol (one thread each).
 hipError_t launch_gather_slots(const int* slot_dst, const int* slot_ptr, const int* ent_pidx,

@@ -1046,17 +1046,80 @@ __device__ __forceinline__ EntDesc full_block(const EntDesc& src) {
   return E;
 }
 
-template <int NWAVE, int NCMAX, int LMAX, int FULLU>
-__device__ __forceinline__ void wave_fwd_one(const LocalParams& a, int eid, double* lds) {
-  if constexpr (FULLU > 0) {
-    const EntDesc E = full_block<FULLU>(a.ents[eid]);
-    wave_fwd_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
+// A face of U x U own cells on a plane of axis NAX, bounded by vertex
+// planes on both of its open axes (the full faces of coarsening U + 1; on a
+// 2-D grid, NAX = 2, the full dual blocks): compile-time geometry as for the
+// full blocks.
+template <int U, int NAX>
+__device__ __forceinline__ EntDesc full_face(const EntDesc& src) {
+  EntDesc E = src;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    E.uext[k] = k == NAX ? 1 : U;
+    E.cext[k] = k == NAX ? 1 : U + 2;
+    E.clo[k] = k == NAX ? src.ulo[k] : src.ulo[k] - 1;
+  }
+  E.open_mask = 7 & ~(1 << NAX);
+  E.bounded_mask = 7 & ~(1 << NAX);
+  E.nc = 4;
+  E.nu = U * U;
+  return E;
+}
+
+// Plane axis of E if E has the shape full_face<U, axis> fixes, else -1
+// (the host orders the face list by the same test).
+template <int U>
+__device__ __forceinline__ int full_face_axis(const EntDesc& E) {
+  if (E.nc != 4 || E.nu != U * U || E.bounded_mask != E.open_mask) return -1;
+  int nax = -1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if ((E.open_mask >> k) & 1) {
+      if (E.uext[k] != U || E.cext[k] != U + 2 || E.clo[k] != E.ulo[k] - 1) return -1;
+    } else {
+      if (nax >= 0 || E.uext[k] != 1 || E.cext[k] != 1 || E.clo[k] != E.ulo[k]) return -1;
+      nax = k;
+    }
+  }
+  return nax;
+}
+
+// FULLU codes of the kernels: 0 any entity, U full U^3 blocks only,
+// faces_code(U) any face, the full U x U faces through a body of their own
+// for each plane axis (one launch for all: a face's wave lives for tens of
+// microseconds, so a launch per axis would leave the device part-empty in
+// every launch's tail).
+constexpr int faces_code(int u) { return 64 + u; }
+
+// Run BODY on eid's entity with the geometry the launch fixes.
+template <int FULLU, typename Body>
+__device__ __forceinline__ void with_shape(const LocalParams& a, int eid, Body&& body) {
+  const EntDesc& G = a.ents[eid];
+  if constexpr (FULLU >= 64) {
+    constexpr int U = FULLU - 64;
+    const int nax = __builtin_amdgcn_readfirstlane(full_face_axis<U>(G));
+    if (nax == 0)
+      body(full_face<U, 0>(G));
+    else if (nax == 1)
+      body(full_face<U, 1>(G));
+    else if (nax == 2)
+      body(full_face<U, 2>(G));
+    else
+      body(G);
+  } else if constexpr (FULLU > 0) {
+    body(full_block<FULLU>(G));
   } else {
-    wave_fwd_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
+    body(G);
   }
 }
 
-// FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks.
+template <int NWAVE, int NCMAX, int LMAX, int FULLU>
+__device__ __forceinline__ void wave_fwd_one(const LocalParams& a, int eid, double* lds) {
+  with_shape<FULLU>(a, eid, [&](const EntDesc& E) { wave_fwd_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds); });
+}
+
+// FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks;
+// FULLU = faces_code(U): faces, the full U x U ones with their shape fixed.
 // MULTI: a fixed grid strides over (problem, entity) items of many problems.
 template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
 __global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
@@ -1421,12 +1484,7 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
 
 template <int NWAVE, int NCMAX, int LMAX, int FULLU>
 __device__ __forceinline__ void wave_adj_one(const LocalParams& a, int eid, double* lds) {
-  if constexpr (FULLU > 0) {
-    const EntDesc E = full_block<FULLU>(a.ents[eid]);
-    wave_adj_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds);
-  } else {
-    wave_adj_body<NWAVE, NCMAX, LMAX>(a, a.ents[eid], eid, lds);
-  }
+  with_shape<FULLU>(a, eid, [&](const EntDesc& E) { wave_adj_body<NWAVE, NCMAX, LMAX>(a, E, eid, lds); });
 }
 
 template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
@@ -1699,7 +1757,8 @@ int wave_class(const LocalParams& p) {
 }
 
 int wave_class_uni_cap(const LocalParams& p, int klass) {
-  return klass == kClassWave441 ? wave_uni_cap<1>(p) : wave_uni_cap<4>(p);
+  const bool one_wave = klass == kClassWave441 || klass == kClassFaces3 || klass == kClassFaces7;
+  return one_wave ? wave_uni_cap<1>(p) : wave_uni_cap<4>(p);
 }
 
 hipError_t launch_wave_multi(const LocalParams& p, int klass, bool adj, hipStream_t s) {
@@ -1712,6 +1771,8 @@ hipError_t launch_wave_multi(const LocalParams& p, int klass, bool adj, hipStrea
     case kClassWave487: return launch_wave_t<4, 8, 7, 0, true>(p, adj, s);
     case kClassFull3: return launch_wave_t<4, 8, 3, 3, true>(p, adj, s);
     case kClassFull7: return launch_wave_t<4, 8, 7, 7, true>(p, adj, s);
+    case kClassFaces3: return launch_wave_t<1, 4, 1, faces_code(3), true>(p, adj, s);
+    case kClassFaces7: return launch_wave_t<1, 4, 1, faces_code(7), true>(p, adj, s);
     default: return hipErrorInvalidConfiguration;
   }
 }
@@ -1720,6 +1781,14 @@ hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s
   if (p.nent == 0) return hipSuccess;
   if (u == 7) return launch_wave_t<4, 8, 7, 7>(p, adj, s);
   if (u == 3) return launch_wave_t<4, 8, 3, 3>(p, adj, s);
+  return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_wave_faces(const LocalParams& p, int u, bool adj, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!wave_path_fits(p) || p.nc_cap > 4 || p.col_cap > 1) return hipErrorInvalidConfiguration;
+  if (u == 7) return launch_wave_t<1, 4, 1, faces_code(7)>(p, adj, s);
+  if (u == 3) return launch_wave_t<1, 4, 1, faces_code(3)>(p, adj, s);
   return hipErrorInvalidConfiguration;
 }
 
