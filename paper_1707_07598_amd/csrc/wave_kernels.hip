@@ -750,12 +750,28 @@ __device__ void load_phi_table(const EntDesc& E, const LocalParams& a, double* p
       for (int q = 0; q < 8; ++q)
         if (q < nc) v[q] = pv[r0 + q];
     } else {
-      for (int e = r0; e < r1; ++e) {
-        const int vid = a.pcol[e];
-        const double val = pv[e];
+      // a closure cell off the own box lies on a lower-dimensional entity:
+      // its row holds at most four corners (a face cell), read at once; any
+      // further entries in a loop
+      int col[4];
+      double val[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool in = r0 + t < r1;
+        col[t] = in ? a.pcol[r0 + t] : -1;
+        val[t] = in ? pv[r0 + t] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (q < nc && E.vid[q] == vid) v[q] = val;
+          if (q < nc && E.vid[q] == col[t]) v[q] = val[t];
+      for (int e = r0 + 4; e < r1; ++e) {
+        const int vid = a.pcol[e];
+        const double vv = pv[e];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nc && E.vid[q] == vid) v[q] = vv;
       }
     }
 #pragma unroll
@@ -796,6 +812,11 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia0 = lane % w.lw, ib0 = lane / w.lw;
   const bool valid = ia0 < w.Ua && ib0 < w.Ub;
+  // one own cell a lane (the one-wave entities): the offset of its S_k row,
+  // read ahead of the solve
+  int own_row = 0;
+  if constexpr (NWAVE == 1)
+    if (valid) own_row = a.prow[w.g0 + ia0 * w.ga + ib0 * w.gb];
   Column<LMAX> C;
   if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead from here on; pbuf aliases it
@@ -906,7 +927,7 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
       } else {
         x = y[k] / S.dsq[u];
       }
-      a.pval[a.prow[gid] + c] = x;
+      a.pval[(NWAVE == 1 ? own_row : a.prow[gid]) + c] = x;
       S.phi[c * ncl + ci] = x;
     }
   };
@@ -1122,7 +1143,7 @@ __device__ __forceinline__ void wave_fwd_one(const LocalParams& a, int eid, doub
 // FULLU = faces_code(U): faces, the full U x U ones with their shape fixed.
 // MULTI: a fixed grid strides over (problem, entity) items of many problems.
 template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_fwd(LocalParams a) {
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE == 1 && !MULTI ? 5 : (NWAVE <= 4 ? 2 : 1))) void k_wave_fwd(LocalParams a) {
   extern __shared__ double lds[];
   if constexpr (MULTI) {
     for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
@@ -1149,7 +1170,14 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   const WGeo w = wave_geo(E, a.g);
   const int ncl = E.cext[0] * E.cext[1] * E.cext[2];
-  double* mus = a.mu_scratch + size_t(eid) * NCMAX * a.nu_cap;  // mu_c on own cells
+  // the arrays of the descriptor that are indexed per lane are read from
+  // memory: indexed so, a register copy of the descriptor (the shapes fixed
+  // at compile time) would live in scratch memory
+  const EntDesc& D = a.ents[eid];
+  // mu_c on own cells: for a one-wave entity in its plane buffers, dead once
+  // the lockstep solves of its corners are done (4 nu <= 6 nu of that
+  // region); else in the entity's slice of a global scratch
+  double* mus = NWAVE == 1 ? S.pbuf : a.mu_scratch + size_t(eid) * NCMAX * a.nu_cap;
   load_phi_table<BLOCK>(E, a, S.phi, false);
   // M_E = sum_j t_j lambda_j^T on the corners; t and lambda of the corners
   // are staged, a chunk of sources at a time, through the plane buffers
@@ -1163,7 +1191,7 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
       for (int i = threadIdx.x; i < 2 * nc * nj; i += BLOCK) {
         const int which = i / (nc * nj), r = i % (nc * nj), q = r / nj, j = r % nj;
         const double* src = which ? a.lam : a.t;
-        tl[i] = src[size_t(j0 + j) * a.ncoarse + E.vid[q]];
+        tl[i] = src[size_t(j0 + j) * a.ncoarse + D.vid[q]];
       }
       __syncthreads();
       if (threadIdx.x < nc * nc) {
@@ -1187,12 +1215,12 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
   // receiver slots of the pushes across each side of the closure
   if (threadIdx.x < 48) {
     const int side = threadIdx.x >> 3, c = threadIdx.x & 7;
-    const int te = E.side_ent[side];
+    const int te = D.side_ent[side];
     int base = -1;
     if (a.push && te >= 0 && c < nc) {
       const EntDesc& R = a.recv[te];
-      const int ct = corner_in(R, E.vid[c]);
-      if (ct >= 0) base = R.inbase + (E.side_slot[side] * R.nc + ct) * R.nu;
+      const int ct = corner_in(R, D.vid[c]);
+      if (ct >= 0) base = R.inbase + (D.side_slot[side] * R.nc + ct) * R.nu;
       if (c == 0) {
         const int s1 = R.uext[0], s2 = R.uext[0] * R.uext[1];
         S.sgeo[3 * side + 0] = s1;
@@ -1421,7 +1449,7 @@ __device__ __forceinline__ void wave_adj_body(const LocalParams& a, const EntDes
       wave_sync_lds();  // the next corner's CG rewrites this wave's buffer
     }
   }
-  __threadfence_block();
+  if constexpr (NWAVE > 1) __threadfence_block();  // mu_c in global memory, read by the other waves
   __syncthreads();
   if (threadIdx.x == 0 && a.ent_it) {
     int itm = 0;
