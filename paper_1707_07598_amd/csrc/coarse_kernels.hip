@@ -81,6 +81,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = red[i];
+    // four partials in flight at a time: with all of them loaded at once the
+    // 1024-thread PCG kernel spills (132 bytes of scratch at 4 rows a thread)
+#pragma unroll 4
     for (int w = 1; w < NW; ++w) s += red[w * NV + i];
     v[i] = s;
   }
@@ -91,16 +94,17 @@ __device__ __forceinline__ int agg_index(const CoarseDefl& d, int x, int y, int 
 }
 
 // out[a] = sum of stage over the vertices of aggregate a, 16 lanes per
-// aggregate, each lane striding over the aggregate's vertex list (from the
-// table d.arows) in a fixed order.
-template <int BLOCK, typename Pos>
-__device__ __forceinline__ void aggregate_sums(const double* stage, const CoarseDefl& d, double* out, Pos pos) {
+// aggregate, each lane striding over the aggregate's vertex list in a fixed
+// order.  aoff: the list offsets of the na aggregates (na + 1); apos: the
+// position in stage of each listed vertex (both in LDS).
+template <int BLOCK>
+__device__ __forceinline__ void aggregate_sums(const double* stage, int na, const int* aoff, const int* apos,
+                                               double* out) {
   const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
-  const int* rows = d.arows + d.na + 1;
-  for (int a = grp; a < d.na; a += BLOCK / 16) {
-    const int k0 = d.arows[a], k1 = d.arows[a + 1];
+  for (int a = grp; a < na; a += BLOCK / 16) {
+    const int k0 = aoff[a], k1 = aoff[a + 1];
     double s = 0.0;
-    for (int k = k0 + l; k < k1; k += 16) s += stage[pos(rows[k])];
+    for (int k = k0 + l; k < k1; k += 16) s += stage[apos[k]];
     s = row16_sum(s);
     if (l == 0) out[a] = s;
   }
@@ -258,9 +262,16 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
   double* einv = redB + NW * 4;        // DEFL: na * na
   double* sv = einv + (DEFL ? d.na * d.na : 0);  // DEFL: 64
   double* yv = sv + 64;                // DEFL: 64
+  // DEFL: the aggregates' vertex-list offsets (na + 1 <= 65) and the LDS
+  // position of every listed vertex, read from the table once
+  int* aoff = reinterpret_cast<int*>(yv + 64);
+  int* apos = aoff + 72;
   for (int i = threadIdx.x; i < pn; i += BLOCK) lds[i] = 0.0;
-  if (DEFL)
+  if (DEFL) {
     for (int i = threadIdx.x; i < d.na * d.na; i += BLOCK) einv[i] = d.einv[i];
+    for (int a = threadIdx.x; a <= d.na; a += BLOCK) aoff[a] = d.arows[a];
+    for (int k = threadIdx.x; k < nc; k += BLOCK) apos[k] = pos(d.arows[d.na + 1 + k]);
+  }
   __syncthreads();
   const double* b = rhs + size_t(blockIdx.x) * nc;
   double* xo = xout + size_t(blockIdx.x) * nc;
@@ -291,7 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
 #pragma unroll
     for (int q = 0; q < RPT; ++q) p[pos(row(q))] = r[q];
     __syncthreads();
-    aggregate_sums<BLOCK>(p, d, sv, pos);
+    aggregate_sums<BLOCK>(p, d.na, aoff, apos, sv);
     __syncthreads();
     // y = E^-1 s: 16 lanes per row of E^-1 (symmetric, read along a row),
     // each lane a strided share of the columns, then the row sum
@@ -427,14 +438,64 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_pcg(const double* __restrict__
       }
       r[q] -= alpha * ap[q];
     }
-    if (DEFL) coarse_correction();
     double s2[2] = {0.0, 0.0};
+    if constexpr (DEFL) {
+      // r.z = r.D^-1 r + y.s with s = Z^T r and y = E^-1 s, so the sums of
+      // r.r and r.D^-1 r share the barriers of the aggregate correction:
+      // r staged in the LDS copy of p (every thread is past its stencil
+      // reads) together with their wave sums ...
+      const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      s2[0] += r[q] * r[q];
-      s2[1] += r[q] * zrow(q);
+      for (int q = 0; q < RPT; ++q) {
+        p[pos(row(q))] = r[q];
+        s2[0] += r[q] * r[q];
+        s2[1] += r[q] * (r[q] * dinv[q]);
+      }
+      s2[0] = wsum(s2[0]);
+      s2[1] = wsum(s2[1]);
+      if (lane == 0) {
+        redB[2 * wid] = s2[0];
+        redB[2 * wid + 1] = s2[1];
+      }
+      __syncthreads();
+      // ... s and the workgroup sums ...
+      aggregate_sums<BLOCK>(p, d.na, aoff, apos, sv);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        double t = redB[i];
+#pragma unroll 4  // (see block_sum)
+        for (int w = 1; w < NW; ++w) t += redB[2 * w + i];
+        s2[i] = t;
+      }
+      __syncthreads();
+      // ... y, and the wave sums of y_t s_t (redA: its p.Ap sums were read
+      // before the first barrier above)
+      double ys = 0.0;
+      for (int t = int(threadIdx.x) >> 4; t < d.na; t += BLOCK / 16) {
+        const int l = threadIdx.x & 15;
+        double y = 0.0;
+        for (int c = l; c < d.na; c += 16) y += einv[t * d.na + c] * sv[c];
+        y = row16_sum(y);
+        if (l == 0) {
+          yv[t] = y;
+          ys += y * sv[t];
+        }
+      }
+      ys = wsum(ys);
+      if (lane == 0) redA[wid] = ys;
+      __syncthreads();
+      double yst = redA[0];
+#pragma unroll 4  // (see block_sum)
+      for (int w = 1; w < NW; ++w) yst += redA[w];
+      s2[1] += yst;
+    } else {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        s2[0] += r[q] * r[q];
+        s2[1] += r[q] * zrow(q);
+      }
+      block_sum<NW, 2>(s2, redB);
     }
-    block_sum<NW, 2>(s2, redB);
     last = uniform(s2[0]);
     if (s2[0] <= tol2 * bb) break;
     if (s2[0] != s2[0]) {
@@ -830,7 +891,10 @@ int qm_rows(int ldk, int ncx) {
 
 size_t pcg_lds_bytes(int ldk, int pad, int na, int qm = 0) {
   const size_t pn = qm ? size_t(qm) * (kBlock + 2 * (pad / qm + 2)) : size_t(ldk) + 2 * pad;
-  return (pn + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128) * sizeof(double);
+  // with aggregates: their list offsets (72 ints) and the LDS position of
+  // every row (ldk ints)
+  const size_t tab = na > 0 ? (72 + size_t(ldk) + 1) / 2 : 0;
+  return (pn + 2 * (kBlock / kWave) * 4 + size_t(na) * na + 128 + tab) * sizeof(double);
 }
 
 size_t setup_lds_bytes(int na) { return 2 * size_t(na) * na * sizeof(double); }
