@@ -155,6 +155,7 @@ struct msfv_problem {
   DevBuf<int> d_blist;
   std::vector<int> h_blist;
   int full_u = 0, nfull = 0, nrest = 0;
+  int edge_line = 0;  // longest closure line of an edge (cells)
   // faces in launch order: the full faces of face_u x face_u own cells
   // (nface_full, grouped by plane axis), then the others (nface_rest);
   // faces_one_launch: the others fit the same wave kernel
@@ -539,6 +540,7 @@ msfv::LocalParams local_params(msfv_problem* p, int kind, bool adj) {
   if (kind == 1) {
     lp.ents = p->d_edges.ptr;
     lp.nent = int(P.edges.size());
+    lp.line_cap = p->edge_line;
     return lp;
   }
   if (kind == 2) {
@@ -1019,6 +1021,10 @@ msfv_status msfv_create(const msfv_config* cfg, void* hip_stream, msfv_problem**
                           std::string(#expr) + ": " + hipGetErrorString(e_)));                 \
   } while (0)
   HIP_OR_CLEAN(p->d_edges.upload(P.edges, s));
+  for (const auto& E : P.edges) {
+    const int k = (E.open_mask & 1) ? 0 : ((E.open_mask & 2) ? 1 : 2);
+    p->edge_line = std::max(p->edge_line, E.cext[k]);
+  }
   HIP_OR_CLEAN(p->d_faces.upload(P.faces, s));
   HIP_OR_CLEAN(p->d_blocks.upload(P.blocks, s));
   HIP_OR_CLEAN(p->d_prow.upload(P.prow, s));
@@ -1585,6 +1591,7 @@ msfv_status shared_build(msfv_batch* b, msfv_batch::Pipeline* pl) {
     c.col_cap = std::max(c.col_cap, lp.col_cap);
     c.nc_cap = std::max(c.nc_cap, lp.nc_cap);
     c.plane_cap = std::max(c.plane_cap, lp.plane_cap);
+    c.line_cap = std::max(c.line_cap, lp.line_cap);
     for (int k = 0; k < count; ++k) g->items.push_back(make_int2(pid, ids ? ids[k] : k));
     return MSFV_OK;
   };

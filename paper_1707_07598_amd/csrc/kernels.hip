@@ -1078,26 +1078,77 @@ __device__ __forceinline__ void edge_phi(const EntDesc& E, const EdgeLine& L, co
   }
 }
 
+// The forward and adjoint edge kernels keep an edge's closure line (LM
+// cells at most: 9 for coarsening up to 8, 17 up to 16) in registers: every
+// loop over the line is unrolled with the edge's own length as a predicate,
+// so no array is indexed at run time (indexed so, they would live in scratch
+// memory).  T[i]: transmissibility between line cells i and i + 1.
+template <int LM>
+struct EdgeRow {
+  int k, len, base, st, u0;
+  double T[LM];
+  double cum[LM];  // cumulative resistances: cum[i] = sum_{f < i} 1 / T[f], constant past the line's end
+};
+
+template <int LM>
+__device__ __forceinline__ void edge_row(const EntDesc& E, const GridInfo& g, const double* sigma,
+                                         EdgeRow<LM>& L) {
+  L.k = (E.open_mask & 1) ? 0 : ((E.open_mask & 2) ? 1 : 2);
+  L.len = E.cext[L.k];
+  L.base = E.clo[0] + g.s1 * E.clo[1] + g.s2 * E.clo[2];
+  L.st = gstride_of(g, L.k);
+  L.u0 = E.ulo[L.k] - E.clo[L.k];
+  double sg[LM];
+#pragma unroll
+  for (int i = 0; i < LM; ++i) sg[i] = i < L.len ? sigma[L.base + i * L.st] : 1.0;
+#pragma unroll
+  for (int i = 0; i < LM; ++i) L.T[i] = (i + 1 < LM && i + 1 < L.len) ? harm(sg[i], sg[i + 1 < LM ? i + 1 : i]) : 0.0;
+  L.cum[0] = 0.0;
+#pragma unroll
+  for (int i = 0; i + 1 < LM; ++i) L.cum[i + 1] = i + 1 < L.len ? L.cum[i] + 1.0 / L.T[i] : L.cum[i];
+}
+
+// basis values of the edge's corners at line position i (i fixed at compile
+// time after unrolling)
+template <int LM>
+__device__ __forceinline__ void edge_phi_at(const EntDesc& E, const EdgeRow<LM>& L, int lagrange, int i,
+                                            double* phi) {
+  if (E.nc == 1) {
+    phi[0] = 1.0;
+    phi[1] = 0.0;
+    return;
+  }
+  if (lagrange) {
+    const double h = L.len - 1;
+    phi[0] = (h - i) / h;
+    phi[1] = double(i) / h;
+  } else {
+    const double R = L.cum[LM - 1];
+    phi[0] = (R - L.cum[i]) / R;
+    phi[1] = L.cum[i] / R;
+  }
+}
+
+template <int LM>
 __device__ __forceinline__ void edge_fwd_one(const LocalParams& a, int e, int lagrange) {
-  const EntDesc E = a.ents[e];
-  EdgeLine L;
-  edge_line(E, a.g, a.sig, L);
-  double cum[kMaxLine];
-  cum[0] = 0.0;
-  for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
-  for (int q = 0; q < E.nu; ++q) {
-    const int i = L.u0 + q;
+  const EntDesc& E = a.ents[e];
+  EdgeRow<LM> L;
+  edge_row<LM>(E, a.g, a.sig, L);
+#pragma unroll
+  for (int i = 0; i < LM; ++i) {
+    if (i < L.u0 || i >= L.u0 + E.nu) continue;
     double phi[2];
-    edge_phi(E, L, cum, lagrange, i, phi);
+    edge_phi_at<LM>(E, L, lagrange, i, phi);
     const int row = a.prow[L.base + i * L.st];
     for (int c = 0; c < E.nc; ++c) a.pval[row + c] = phi[c];
   }
   double k00 = 0.0, k01 = 0.0, k11 = 0.0;
-  for (int i = 0; i + 1 < L.len; ++i) {
+#pragma unroll
+  for (int i = 0; i + 1 < LM; ++i) {
+    if (i + 1 >= L.len || E.nc == 1) continue;
     double pa[2], pb2[2];
-    edge_phi(E, L, cum, lagrange, i, pa);
-    edge_phi(E, L, cum, lagrange, i + 1, pb2);
-    if (E.nc == 1) continue;
+    edge_phi_at<LM>(E, L, lagrange, i, pa);
+    edge_phi_at<LM>(E, L, lagrange, i + 1, pb2);
     const double d0 = pa[0] - pb2[0], d1 = pa[1] - pb2[1];
     k00 += L.T[i] * d0 * d0;
     k01 += L.T[i] * d0 * d1;
@@ -1113,10 +1164,11 @@ __device__ __forceinline__ void edge_fwd_one(const LocalParams& a, int e, int la
   }
 }
 
-__global__ void k_edge_fwd(LocalParams a, int lagrange) {
+template <int LM>
+__global__ __launch_bounds__(64) void k_edge_fwd(LocalParams a, int lagrange) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nent) return;
-  edge_fwd_one(a, e, lagrange);
+  edge_fwd_one<LM>(a, e, lagrange);
 }
 
 // Tangent of the edge basis along dm (Sec. 4.5, forward mode): with
@@ -1180,19 +1232,19 @@ __global__ void k_edge_tan(LocalParams a, int lagrange) {
   a.kent[E.kbase + 3] = k11;
 }
 
+template <int LM>
 __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int lagrange) {
-  const EntDesc E = a.ents[e];
-  EdgeLine L;
-  edge_line(E, a.g, a.sig, L);
+  const EntDesc& E = a.ents[e];
+  EdgeRow<LM> L;
+  edge_row<LM>(E, a.g, a.sig, L);
   const long long N = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
   double* Wk = a.W + L.k * N;
   if (E.nc == 1) {  // strip: s = 1 for every m, nothing depends on m
-    for (int i = 0; i + 1 < L.len; ++i) Wk[L.base + i * L.st] = 0.0;
+#pragma unroll
+    for (int i = 0; i + 1 < LM; ++i)
+      if (i + 1 < L.len) Wk[L.base + i * L.st] = 0.0;
     return;
   }
-  double cum[kMaxLine];
-  cum[0] = 0.0;
-  for (int i = 0; i + 1 < L.len; ++i) cum[i + 1] = cum[i] + 1.0 / L.T[i];
   double M[4] = {0, 0, 0, 0};
   // unrolled: the loads of several sources in flight together (the sums
   // keep their order)
@@ -1206,10 +1258,17 @@ __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int la
     M[3] += t1 * l1;
   }
   const double S[4] = {2 * M[0], M[1] + M[2], M[1] + M[2], 2 * M[3]};
-  // loads on own cells (closure positions 1 .. len-2 for a bounded edge)
-  double z0[kMaxLine], z1[kMaxLine];
-  for (int q = 0; q < E.nu; ++q) {
-    const int i = L.u0 + q;
+  // mu = (A^E_EE)^{-1} z on the own cells (line positions u0 .. u0 + nu - 1;
+  // 1 .. len - 2 for a bounded edge): the loads z first, then the Thomas
+  // algorithm in place (an M-matrix, no pivoting).  Lagrange edges have no
+  // local problem: mu = 0.
+  double mu0[LM], mu1[LM];
+  const int i0 = L.u0, i1 = L.u0 + E.nu - 1;
+#pragma unroll
+  for (int i = 0; i < LM; ++i) {
+    mu0[i] = mu1[i] = 0.0;
+    if (lagrange || i < i0 || i > i1) continue;
+    const int q = i - L.u0;
     double l0 = 0.0, l1 = 0.0;
     for (int s = 0; s < E.nslot; ++s) {
       l0 += a.inbuf[E.inbase + (s * 2 + 0) * E.nu + q];
@@ -1221,43 +1280,55 @@ __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int la
         l1 += a.sload[a.eidx[ee] * 8 + 1];
       }
     double pu[2], pn[2];
-    edge_phi(E, L, cum, lagrange, i, pu);
-    for (int side = -1; side <= 1; side += 2) {
-      const int nbp = i + side;
-      const int f = side < 0 ? i - 1 : i;
-      edge_phi(E, L, cum, lagrange, nbp, pn);
+    edge_phi_at<LM>(E, L, lagrange, i, pu);
+    // the own cells of a bounded edge have both line neighbours (the
+    // clamped positions below only keep the unrolled indices in range)
+    const int kLo = i > 0 ? i - 1 : 0, kHi = i + 1 < LM ? i + 1 : LM - 1;
+    edge_phi_at<LM>(E, L, lagrange, kLo, pn);
+    {
       const double d0 = pu[0] - pn[0], d1 = pu[1] - pn[1];
-      l0 -= L.T[f] * (S[0] * d0 + S[2] * d1);
-      l1 -= L.T[f] * (S[1] * d0 + S[3] * d1);
+      l0 -= L.T[kLo] * (S[0] * d0 + S[2] * d1);
+      l1 -= L.T[kLo] * (S[1] * d0 + S[3] * d1);
     }
-    z0[i] = l0;
-    z1[i] = l1;
+    edge_phi_at<LM>(E, L, lagrange, kHi, pn);
+    {
+      const double d0 = pu[0] - pn[0], d1 = pu[1] - pn[1];
+      l0 -= L.T[i] * (S[0] * d0 + S[2] * d1);
+      l1 -= L.T[i] * (S[1] * d0 + S[3] * d1);
+    }
+    mu0[i] = l0;
+    mu1[i] = l1;
   }
-  // mu = (A^E_EE)^{-1} z by the Thomas algorithm (an M-matrix, no pivoting)
-  double mu0[kMaxLine], mu1[kMaxLine];
-  for (int i = 0; i < L.len; ++i) mu0[i] = mu1[i] = 0.0;
   if (!lagrange) {
-    double cp[kMaxLine];
-    const int i0 = L.u0, i1 = L.u0 + E.nu - 1;
-    for (int i = i0; i <= i1; ++i) {
-      const double lo = (i > 0) ? L.T[i - 1] : 0.0;
-      const double hi = (i + 1 < L.len) ? L.T[i] : 0.0;
+    double cp[LM];
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      cp[i] = 0.0;
+      if (i < i0 || i > i1) continue;
+      const int im = i > 0 ? i - 1 : 0;
+      const bool first = !(i > 0 && i > i0);
+      const double lo = i > 0 ? L.T[im] : 0.0;
+      const double hi = i + 1 < L.len ? L.T[i] : 0.0;
       const double diag = lo + hi;
-      const double sub = (i > i0) ? -lo : 0.0;
-      const double den = diag - sub * ((i > i0) ? cp[i - 1] : 0.0);
+      const double sub = first ? 0.0 : -lo;
+      const double den = diag - sub * (first ? 0.0 : cp[im]);
       cp[i] = (i < i1) ? -hi / den : 0.0;
-      mu0[i] = (z0[i] - sub * ((i > i0) ? mu0[i - 1] : 0.0)) / den;
-      mu1[i] = (z1[i] - sub * ((i > i0) ? mu1[i - 1] : 0.0)) / den;
+      mu0[i] = (mu0[i] - sub * (first ? 0.0 : mu0[im])) / den;
+      mu1[i] = (mu1[i] - sub * (first ? 0.0 : mu1[im])) / den;
     }
-    for (int i = i1 - 1; i >= i0; --i) {
+#pragma unroll
+    for (int i = LM - 2; i >= 0; --i) {
+      if (i < i0 || i >= i1) continue;
       mu0[i] -= cp[i] * mu0[i + 1];
       mu1[i] -= cp[i] * mu1[i + 1];
     }
   }
-  for (int i = 0; i + 1 < L.len; ++i) {
+#pragma unroll
+  for (int i = 0; i + 1 < LM; ++i) {
+    if (i + 1 >= L.len) continue;
     double pa[2], pb2[2];
-    edge_phi(E, L, cum, lagrange, i, pa);
-    edge_phi(E, L, cum, lagrange, i + 1, pb2);
+    edge_phi_at<LM>(E, L, lagrange, i, pa);
+    edge_phi_at<LM>(E, L, lagrange, i + 1, pb2);
     const double d0 = pa[0] - pb2[0], d1 = pa[1] - pb2[1];
     const double quad = d0 * (M[0] * d0 + M[1] * d1) + d1 * (M[2] * d0 + M[3] * d1);
     const double w = -((mu0[i] - mu0[i + 1]) * d0 + (mu1[i] - mu1[i + 1]) * d1) - quad;
@@ -1265,22 +1336,24 @@ __device__ __forceinline__ void edge_adj_one(const LocalParams& a, int e, int la
   }
 }
 
-__global__ void k_edge_adj(LocalParams a, int lagrange) {
+template <int LM>
+__global__ __launch_bounds__(64) void k_edge_adj(LocalParams a, int lagrange) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nent) return;
-  edge_adj_one(a, e, lagrange);
+  edge_adj_one<LM>(a, e, lagrange);
 }
 
 // edges of many problems: one thread an item
-__global__ void k_edge_multi(LocalParams a, int adj) {
+template <int LM>
+__global__ __launch_bounds__(128) void k_edge_multi(LocalParams a, int adj) {
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= a.nent) return;
   const int2 w = a.items[it];
   const LocalParams& A = a.multi[w.x];
   if (adj)
-    edge_adj_one(A, w.y, A.lagrange);
+    edge_adj_one<LM>(A, w.y, A.lagrange);
   else
-    edge_fwd_one(A, w.y, A.lagrange);
+    edge_fwd_one<LM>(A, w.y, A.lagrange);
 }
 
 // ---------------------------------------------------------------------------
@@ -1790,7 +1863,11 @@ hipError_t launch_local_multi(const LocalParams& p, int klass, bool adj, hipStre
 hipError_t launch_edge_multi(const LocalParams& p, bool adj, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
   if (!p.multi || !p.items) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_edge_multi, dim3((p.nent + 127) / 128), dim3(128), 0, s, p, adj ? 1 : 0);
+  if (p.line_cap <= 0 || p.line_cap > kMaxLine) return hipErrorInvalidConfiguration;
+  if (p.line_cap <= 9)
+    hipLaunchKernelGGL(k_edge_multi<9>, dim3((p.nent + 127) / 128), dim3(128), 0, s, p, adj ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_edge_multi<kMaxLine>, dim3((p.nent + 127) / 128), dim3(128), 0, s, p, adj ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1805,13 +1882,21 @@ hipError_t launch_check_finite(const double* m, long long n, int* status, hipStr
 
 hipError_t launch_edge_fwd(const LocalParams& p, int lagrange, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge_fwd, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  if (p.line_cap <= 0 || p.line_cap > kMaxLine) return hipErrorInvalidConfiguration;
+  if (p.line_cap <= 9)
+    hipLaunchKernelGGL(k_edge_fwd<9>, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  else
+    hipLaunchKernelGGL(k_edge_fwd<kMaxLine>, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
   return hipGetLastError();
 }
 
 hipError_t launch_edge_adj(const LocalParams& p, int lagrange, hipStream_t s) {
   if (p.nent == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge_adj, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  if (p.line_cap <= 0 || p.line_cap > kMaxLine) return hipErrorInvalidConfiguration;
+  if (p.line_cap <= 9)
+    hipLaunchKernelGGL(k_edge_adj<9>, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
+  else
+    hipLaunchKernelGGL(k_edge_adj<kMaxLine>, dim3((p.nent + 63) / 64), dim3(64), 0, s, p, lagrange);
   return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct LocalParams {
   int col_cap = 0;     // largest own-cell column along the third axis
   int nc_cap = 0;      // largest corner count
   int plane_cap = 0;   // largest zero-padded plane buffer (doubles per wave)
+  int line_cap = 0;    // edges: longest closure line (cells) of the launch
   // adjoint
   const double* t = nullptr;
   const double* lam = nullptr;
