@@ -812,11 +812,14 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
   const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int ia0 = lane % w.lw, ib0 = lane / w.lw;
   const bool valid = ia0 < w.Ua && ib0 < w.Ub;
-  // one own cell a lane (the one-wave entities): the offset of its S_k row,
-  // read ahead of the solve
-  int own_row = 0;
-  if constexpr (NWAVE == 1)
-    if (valid) own_row = a.prow[w.g0 + ia0 * w.ga + ib0 * w.gb];
+  // the offsets of the S_k rows of the lane's own cells, read ahead of the
+  // solves: a store after a solve then waits on no load (a load issued
+  // after the previous corner's stores would wait for them too, the vector
+  // memory counter being in order)
+  int own_row[LMAX];
+#pragma unroll
+  for (int k = 0; k < LMAX; ++k)
+    own_row[k] = (valid && k < w.L) ? a.prow[w.g0 + ia0 * w.ga + ib0 * w.gb + k * w.gc] : 0;
   Column<LMAX> C;
   if (wid < nc && !a.prescribe) load_column<LMAX>(E, w, valid, ia0, ib0, S.tt, C);
   __syncthreads();  // tt is dead from here on; pbuf aliases it
@@ -927,7 +930,7 @@ __device__ __forceinline__ void wave_fwd_body(const LocalParams& a, const EntDes
       } else {
         x = y[k] / S.dsq[u];
       }
-      a.pval[(NWAVE == 1 ? own_row : a.prow[gid]) + c] = x;
+      a.pval[own_row[k] + c] = x;
       S.phi[c * ncl + ci] = x;
     }
   };
