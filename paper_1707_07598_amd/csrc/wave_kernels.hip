@@ -1145,6 +1145,9 @@ __device__ __forceinline__ void wave_fwd_one(const LocalParams& a, int eid, doub
 // FULLU = 0: any entity of the launch; FULLU = U: only full U^3 blocks;
 // FULLU = faces_code(U): faces, the full U x U ones with their shape fixed.
 // MULTI: a fixed grid strides over (problem, entity) items of many problems.
+// The one-wave (face) launches ask for five waves a SIMD, i.e. at most 96
+// VGPRs: the few registers that then spill cost less than the fifth wave
+// gains in hiding the latency of the face's memory reads.
 template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
 __global__ __launch_bounds__(NWAVE * 64, (NWAVE == 1 && !MULTI ? 5 : (NWAVE <= 4 ? 2 : 1))) void k_wave_fwd(LocalParams a) {
   extern __shared__ double lds[];
@@ -1519,7 +1522,7 @@ __device__ __forceinline__ void wave_adj_one(const LocalParams& a, int eid, doub
 }
 
 template <int NWAVE, int NCMAX, int LMAX, int FULLU = 0, bool MULTI = false>
-__global__ __launch_bounds__(NWAVE * 64, (NWAVE <= 4 ? 2 : 1)) void k_wave_adj(LocalParams a) {
+__global__ __launch_bounds__(NWAVE * 64, (NWAVE == 1 && !MULTI ? 5 : (NWAVE <= 4 ? 2 : 1))) void k_wave_adj(LocalParams a) {
   extern __shared__ double lds[];
   if constexpr (MULTI) {
     for (int it = blockIdx.x; it < a.nent; it += gridDim.x) {
