@@ -472,9 +472,18 @@ void full_caps(msfv::LocalParams& lp, int u) {
   lp.plane_cap = msfv::wave_plane(u, u) * u;
 }
 
-// Local solves of the dual blocks: the full blocks through the kernels
-// specialised for their shape, the others through the general ones.
+// Local solves of the dual blocks: the full blocks through the bodies
+// specialised for their shape, the others through the general ones; the
+// forward in one launch where the others fit the same wave kernel, else in
+// two (the adjoint always in two: its two bodies in one kernel spill).
 hipError_t launch_blocks(msfv_problem* p, const msfv::LocalParams& lp, bool adj, hipStream_t s) {
+  if (!adj && p->nfull > 0 && p->nrest > 0 && msfv::wave_path_fits(lp) && lp.nc_cap <= 8 &&
+      (p->full_u == 7 || lp.col_cap <= 3)) {
+    msfv::LocalParams b = lp;
+    b.ent_list = p->d_blist.ptr;
+    b.nent = p->nfull + p->nrest;
+    return msfv::launch_wave_blocks(b, p->full_u, s);
+  }
   if (p->nfull > 0) {
     msfv::LocalParams f = lp;
     full_caps(f, p->full_u);

@@ -182,6 +182,11 @@ hipError_t launch_wave_local(const LocalParams& p, bool adj, hipStream_t s);
 // the same for full dual blocks of u^3 own cells (u = 3 or 7) listed in
 // p.ent_list, with their geometry fixed at compile time
 hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s);
+// forward local solves of all dual blocks of p.ent_list in one launch (caps
+// within the wave path): the full u^3 ones (u = 7, or u = 3 when no column
+// exceeds 3 cells) through the body with their geometry fixed, the others
+// through the general body
+hipError_t launch_wave_blocks(const LocalParams& p, int u, hipStream_t s);
 // and for faces (one cell a lane, caps within one wavefront): the full faces
 // of u x u own cells (u = 3 or 7, bounded by vertex planes on both open
 // axes) through bodies with their geometry fixed, one for each plane axis,

@@ -1108,18 +1108,38 @@ __device__ __forceinline__ int full_face_axis(const EntDesc& E) {
   return nax;
 }
 
+// Whether E has the shape full_block<U> fixes (the host lists the full
+// blocks by the same test).
+template <int U>
+__device__ __forceinline__ bool is_full_block(const EntDesc& E) {
+  if (E.open_mask != 7 || E.bounded_mask != 7 || E.nc != 8 || E.nu != U * U * U) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (E.uext[k] != U || E.cext[k] != U + 2 || E.clo[k] != E.ulo[k] - 1) return false;
+  return true;
+}
+
 // FULLU codes of the kernels: 0 any entity, U full U^3 blocks only,
 // faces_code(U) any face, the full U x U faces through a body of their own
 // for each plane axis (one launch for all: a face's wave lives for tens of
 // microseconds, so a launch per axis would leave the device part-empty in
-// every launch's tail).
+// every launch's tail); blocks_code(U) any dual block, the full U^3 ones
+// through their own body (one launch for the full and the other blocks, for
+// the same reason).
 constexpr int faces_code(int u) { return 64 + u; }
+constexpr int blocks_code(int u) { return 128 + u; }
 
 // Run BODY on eid's entity with the geometry the launch fixes.
 template <int FULLU, typename Body>
 __device__ __forceinline__ void with_shape(const LocalParams& a, int eid, Body&& body) {
   const EntDesc& G = a.ents[eid];
-  if constexpr (FULLU >= 64) {
+  if constexpr (FULLU >= 128) {
+    constexpr int U = FULLU - 128;
+    if (__builtin_amdgcn_readfirstlane(is_full_block<U>(G) ? 1 : 0))
+      body(full_block<U>(G));
+    else
+      body(G);
+  } else if constexpr (FULLU >= 64) {
     constexpr int U = FULLU - 64;
     const int nax = __builtin_amdgcn_readfirstlane(full_face_axis<U>(G));
     if (nax == 0)
@@ -1815,6 +1835,14 @@ hipError_t launch_wave_full(const LocalParams& p, int u, bool adj, hipStream_t s
   if (p.nent == 0) return hipSuccess;
   if (u == 7) return launch_wave_t<4, 8, 7, 7>(p, adj, s);
   if (u == 3) return launch_wave_t<4, 8, 3, 3>(p, adj, s);
+  return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_wave_blocks(const LocalParams& p, int u, hipStream_t s) {
+  if (p.nent == 0) return hipSuccess;
+  if (!wave_path_fits(p) || p.nc_cap > 8) return hipErrorInvalidConfiguration;
+  if (u == 7) return launch_wave_t<4, 8, 7, blocks_code(7)>(p, false, s);
+  if (u == 3 && p.col_cap <= 3) return launch_wave_t<4, 8, 3, blocks_code(3)>(p, false, s);
   return hipErrorInvalidConfiguration;
 }
 
