@@ -26,6 +26,7 @@ CASES = [
     ((18, 10, 7), (5, 3, 3)),     # 2-cell last coarse cells
     ((40, 36, 34), (16, 16, 16)), # r = 16: a dual block of 15^3 own cells (generic kernels)
     ((33, 33, 17), (16, 16, 16)), # r = 16 with one full 7^3 block among 15 x 15 x 7 ones (both paths)
+    ((24, 24, 40), (8, 8, 16)),   # full 7 x 7 faces in the shape-fixed face launch, 7 x 15 faces generic
     ((40, 36), (16, 16)),         # 2-D r = 16: 15^2 own cells, 4 corners (generic kernels)
     ((32, 32), (4, 4)),           # 2-D
     ((23, 17), (5, 6)),           # 2-D truncated
